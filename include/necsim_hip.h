@@ -1,0 +1,183 @@
+/*
+ * necsim_hip.h - C ABI of libnecsim_hip, an MI355X (gfx950) implementation of
+ * the communication-free Independent algorithm for neutral Moran biodiversity
+ * models (Langenstein 2021, arXiv 2108.05815).
+ *
+ * The method (paper chapter "The Declaration of Independence"): every sampled
+ * individual's lineage is traced backwards in time on its own.  Its random
+ * numbers come from a counter-based hash keyed on (seed, indexed location,
+ * time) ("Environmental RNG Priming"), and waiting times are sums of
+ * exponentials restarted at fixed interval boundaries ("Aligning the RNGs of
+ * Colliding Individuals", "Exponential inter-event Times"), so lineages that
+ * meet draw identical numbers from then on and merge with no communication.
+ * At each event a lineage speciates with probability nu, otherwise it moves to
+ * a parent drawn from the dispersal kernel and a uniform deme index ("Summary
+ * of the Independent Algorithm").  Species identities are hashed from the
+ * speciation event; richness is the number of distinct identities among the
+ * samples.  Lineages that reach the same (location, next event time) are
+ * merged after time-aligned horizon rounds ("Deduplicating Redundant
+ * Individuals", Water-Level algorithm).
+ *
+ * Conventions used by every entry point:
+ *   - Return value: NH_OK (0) or a negative NH_E* code; the message of the
+ *     last failure on the calling thread is available from nh_last_error().
+ *   - Ownership: the caller owns every buffer it passes.  nh_scenario_create
+ *     deep-copies its host inputs and owns the device tables until
+ *     nh_scenario_destroy.  Outputs are written only on success.
+ *   - Host vs device pointers: arguments named h_* are host memory, d_* are
+ *     device memory of the current HIP device (for instance a PyTorch tensor's
+ *     data_ptr()).  Streams are hipStream_t passed as void* (NULL = default).
+ *   - Sample ids are dense individual indices in [0, N), N = sum of
+ *     capacities, in row-major cell order then deme index.  Duplicates are
+ *     allowed and give identical species.
+ *   - Results are a pure function of (scenario, seed, sample id): they do not
+ *     depend on the order or partition of the samples, on the batch a job
+ *     runs in, or on any tuning parameter in nh_config.
+ */
+#ifndef NECSIM_HIP_H
+#define NECSIM_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NH_OK 0
+#define NH_EINVAL (-1)   /* invalid argument (see each function) */
+#define NH_ENOMEM (-2)   /* host or device allocation failed, or workspace too small */
+#define NH_EDEVICE (-3)  /* HIP runtime error or kernel-reported failure */
+#define NH_ETIMEOUT (-4) /* the run exceeded nh_config.timeout_s */
+
+#define NH_DISPERSAL_SHARED 0u   /* one alias table over the kernel, shared by every deme */
+#define NH_DISPERSAL_PER_DEME 1u /* one table per habitable deme over weight x target capacity */
+
+typedef struct nh_scenario nh_scenario; /* opaque, library-owned, immutable after creation */
+
+/* Landscape: a width x height torus of demes; capacity is a host array of
+ * height*width u32 in row-major order (cell c = y*width + x). */
+typedef struct {
+    uint32_t width, height;
+    const uint32_t *h_capacity;
+} nh_habitat;
+
+/* Dispersal kernel: (2R+1)^2 non-negative f64 weights on the host, row-major
+ * with row = dy + R and column = dx + R (paper: the dispersal sampler maps a
+ * habitable origin to a habitable target, possibly the origin itself).
+ * mode NH_DISPERSAL_SHARED: parent cell drawn in proportion to the weight;
+ *   every deme must have capacity > 0.
+ * mode NH_DISPERSAL_PER_DEME: parent cell drawn in proportion to weight times
+ *   the target's capacity, uninhabitable targets excluded (a dispersal map
+ *   restricted to habitable cells).  Radius 0 with a 1x1 torus is the paper's
+ *   non-spatial scenario. */
+typedef struct {
+    uint32_t radius;
+    const double *h_weights;
+    uint32_t mode;
+} nh_dispersal;
+
+/* Scenario constants that change the random draws (never tuned):
+ * lambda > 0 is the per-individual turnover rate, delta_t the repriming
+ * interval, a positive power of two with lambda*delta_t <= 2^20. */
+typedef struct {
+    double lambda;
+    double delta_t;
+} nh_params;
+
+/* Tuning knobs; none of them changes any result.  Zero fields take defaults. */
+typedef struct {
+    double horizon0;      /* first cull horizon (time units), default 0.5 */
+    double horizon_growth;/* horizon multiplier per round (> 1), default 1.25 */
+    double horizon_step_max; /* cap on one round's horizon advance, default 4096 */
+    uint32_t block_size;  /* threads per workgroup of the round kernel (64..1024), default 256 */
+    uint32_t blocks_per_cu; /* workgroups per compute unit, default 4 */
+    uint32_t rounds_per_graph; /* round kernels per captured graph, default 8 */
+    uint32_t table_in_lds; /* 1: stage a shared dispersal table in LDS when it fits, default 1 */
+    double timeout_s;     /* wall-clock limit of one run, default 600 */
+} nh_config;
+
+/* Per-job counters of one run. */
+typedef struct {
+    uint64_t events;    /* committed events (speciations + dispersals) of every lane, duplicates included */
+    uint64_t lineages;  /* samples simulated */
+    uint64_t speciated; /* lineages that ended by speciating (representatives) */
+    uint64_t merged;    /* lineages merged into an identical one by culling */
+    uint64_t rounds;    /* horizon rounds the job took part in */
+    uint64_t richness;
+    double device_ms;   /* stream time of the whole run (same for every job of a batch) */
+} nh_stats;
+
+/* One simulate request of a batch.  Device pointers; species_out has n slots. */
+typedef struct {
+    const nh_scenario *scenario;
+    uint64_t seed;
+    const uint64_t *d_sample_ids;
+    uint64_t n;
+    uint64_t *d_species_out;
+    uint64_t *d_richness_out; /* one u64, may be NULL */
+} nh_job;
+
+/* Builds the scenario's tables on the host (Vose alias tables, capacity prefix)
+ * and uploads them to the current device.
+ * Errors: NH_EINVAL if width or height is 0, 2R+1 exceeds width or height,
+ * nu is not in (0, 1], a weight is negative, NaN or infinite, all weights are
+ * zero, a habitable deme has no habitable mass in its kernel, the shared mode
+ * meets a zero-capacity deme, width*height*max(capacity) >= 2^32, lambda is
+ * not positive and finite, delta_t is not a power of two, or
+ * lambda*delta_t > 2^20; NH_ENOMEM / NH_EDEVICE on allocation or copy failure.
+ * params may be NULL (lambda = 1, delta_t = 1). */
+int nh_scenario_create(const nh_habitat *habitat, const nh_dispersal *dispersal, double nu, const nh_params *params,
+                       nh_scenario **out);
+
+void nh_scenario_destroy(nh_scenario *scenario);
+
+/* Number of individuals N (sum of capacities). */
+uint64_t nh_scenario_individuals(const nh_scenario *scenario);
+
+/* Device bytes held by the scenario's tables. */
+uint64_t nh_scenario_table_bytes(const nh_scenario *scenario);
+
+/* Device workspace needed by nh_batch_run for jobs with n_total samples in all
+ * (sum of job sizes) and n_jobs jobs. */
+uint64_t nh_workspace_bytes(uint64_t n_total, uint32_t n_jobs);
+
+/* Scenario tables plus the workspace of one job of n samples: the HBM an
+ * admission controller must reserve for it. */
+uint64_t nh_scenario_footprint_bytes(const nh_scenario *scenario, uint64_t n_samples);
+
+/* Simulates every job in one device run: all lineages of all jobs share the
+ * round kernels (captured in HIP graphs), the cull hash table and the work
+ * queue.  d_workspace must hold nh_workspace_bytes(sum n, n_jobs) bytes of
+ * device memory, 256-byte aligned.  Work is enqueued on `stream`; the call
+ * returns when the results are written (it blocks the calling thread, polling
+ * a host-mapped status word; other streams are not synchronised).
+ * stats (nullable) receives n_jobs entries.  cfg may be NULL.
+ * Errors: NH_EINVAL for a NULL job field with n > 0, a sample id >= N (the
+ * device checks every id), or a bad cfg; NH_ENOMEM if the workspace is too
+ * small; NH_EDEVICE on a HIP error; NH_ETIMEOUT if cfg->timeout_s passes. */
+int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint64_t workspace_bytes,
+                 const nh_config *cfg, nh_stats *stats, void *stream);
+
+/* One job with device buffers; allocates its own workspace (hipMallocAsync on
+ * the stream).  Same semantics as nh_batch_run with one job. */
+int nh_simulate_device(const nh_scenario *scenario, uint64_t seed, const uint64_t *d_sample_ids, uint64_t n,
+                       uint64_t *d_species_out, uint64_t *d_richness_out, const nh_config *cfg, nh_stats *stats,
+                       void *stream);
+
+/* One job with host buffers: uploads the samples, runs, downloads species
+ * (n u64) and the richness.  Blocking; uses the default stream. */
+int nh_simulate(const nh_scenario *scenario, uint64_t seed, const uint64_t *h_sample_ids, uint64_t n,
+                uint64_t *h_species_out, uint64_t *h_richness_out, nh_stats *stats);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *nh_last_error(void);
+
+/* Library version string. */
+const char *nh_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NECSIM_HIP_H */

@@ -1,0 +1,215 @@
+"""Thin ctypes binding of libnecsim_hip (include/necsim_hip.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Functions keep the C names (nh_scenario_create, nh_batch_run, ...); the
+``Scenario`` class and ``simulate`` / ``batch_run`` helpers wrap them for numpy
+arrays and PyTorch device tensors (PyTorch provides device memory and streams).
+
+Importing this module loads ``libnecsim_hip.so`` from the package directory
+and raises ``ImportError`` if it has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnecsim_hip.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_2108_05815_amd/build.py (or __graft_entry__.build())")
+
+_lib = C.CDLL(LIB_PATH)
+
+NH_OK, NH_EINVAL, NH_ENOMEM, NH_EDEVICE, NH_ETIMEOUT = 0, -1, -2, -3, -4
+NH_DISPERSAL_SHARED, NH_DISPERSAL_PER_DEME = 0, 1
+
+
+class nh_habitat(C.Structure):
+    _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("h_capacity", C.POINTER(C.c_uint32))]
+
+
+class nh_dispersal(C.Structure):
+    _fields_ = [("radius", C.c_uint32), ("h_weights", C.POINTER(C.c_double)), ("mode", C.c_uint32)]
+
+
+class nh_params(C.Structure):
+    _fields_ = [("lambda_", C.c_double), ("delta_t", C.c_double)]
+
+
+class nh_config(C.Structure):
+    _fields_ = [("horizon0", C.c_double), ("horizon_growth", C.c_double), ("horizon_step_max", C.c_double),
+                ("block_size", C.c_uint32), ("blocks_per_cu", C.c_uint32), ("rounds_per_graph", C.c_uint32),
+                ("table_in_lds", C.c_uint32), ("timeout_s", C.c_double)]
+
+
+class nh_stats(C.Structure):
+    _fields_ = [("events", C.c_uint64), ("lineages", C.c_uint64), ("speciated", C.c_uint64),
+                ("merged", C.c_uint64), ("rounds", C.c_uint64), ("richness", C.c_uint64),
+                ("device_ms", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class nh_job(C.Structure):
+    _fields_ = [("scenario", C.c_void_p), ("seed", C.c_uint64), ("d_sample_ids", C.c_void_p), ("n", C.c_uint64),
+                ("d_species_out", C.c_void_p), ("d_richness_out", C.c_void_p)]
+
+
+_lib.nh_scenario_create.argtypes = [C.POINTER(nh_habitat), C.POINTER(nh_dispersal), C.c_double,
+                                    C.POINTER(nh_params), C.POINTER(C.c_void_p)]
+_lib.nh_scenario_create.restype = C.c_int
+_lib.nh_scenario_destroy.argtypes = [C.c_void_p]
+_lib.nh_scenario_destroy.restype = None
+_lib.nh_scenario_individuals.argtypes = [C.c_void_p]
+_lib.nh_scenario_individuals.restype = C.c_uint64
+_lib.nh_scenario_table_bytes.argtypes = [C.c_void_p]
+_lib.nh_scenario_table_bytes.restype = C.c_uint64
+_lib.nh_workspace_bytes.argtypes = [C.c_uint64, C.c_uint32]
+_lib.nh_workspace_bytes.restype = C.c_uint64
+_lib.nh_scenario_footprint_bytes.argtypes = [C.c_void_p, C.c_uint64]
+_lib.nh_scenario_footprint_bytes.restype = C.c_uint64
+_lib.nh_batch_run.argtypes = [C.POINTER(nh_job), C.c_uint32, C.c_void_p, C.c_uint64, C.POINTER(nh_config),
+                              C.POINTER(nh_stats), C.c_void_p]
+_lib.nh_batch_run.restype = C.c_int
+_lib.nh_simulate_device.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
+                                    C.POINTER(nh_config), C.POINTER(nh_stats), C.c_void_p]
+_lib.nh_simulate_device.restype = C.c_int
+_lib.nh_simulate.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64), C.c_uint64, C.POINTER(C.c_uint64),
+                             C.POINTER(C.c_uint64), C.POINTER(nh_stats)]
+_lib.nh_simulate.restype = C.c_int
+_lib.nh_last_error.argtypes = []
+_lib.nh_last_error.restype = C.c_char_p
+_lib.nh_version.argtypes = []
+_lib.nh_version.restype = C.c_char_p
+
+# The C names, for callers that want the raw ABI.
+nh_scenario_create = _lib.nh_scenario_create
+nh_scenario_destroy = _lib.nh_scenario_destroy
+nh_scenario_individuals = _lib.nh_scenario_individuals
+nh_scenario_table_bytes = _lib.nh_scenario_table_bytes
+nh_workspace_bytes = _lib.nh_workspace_bytes
+nh_scenario_footprint_bytes = _lib.nh_scenario_footprint_bytes
+nh_batch_run = _lib.nh_batch_run
+nh_simulate_device = _lib.nh_simulate_device
+nh_simulate = _lib.nh_simulate
+nh_last_error = _lib.nh_last_error
+nh_version = _lib.nh_version
+
+EXPORTED = ["nh_scenario_create", "nh_scenario_destroy", "nh_scenario_individuals", "nh_scenario_table_bytes",
+            "nh_workspace_bytes", "nh_scenario_footprint_bytes", "nh_batch_run", "nh_simulate_device",
+            "nh_simulate", "nh_last_error", "nh_version"]
+
+
+class NecsimError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where} failed ({code}): {_lib.nh_last_error().decode()}")
+
+
+def _check(code: int, where: str):
+    if code != NH_OK:
+        raise NecsimError(code, where)
+
+
+def make_config(**kw) -> nh_config:
+    c = nh_config()
+    for k, v in kw.items():
+        if v is not None:
+            setattr(c, k, v)
+    return c
+
+
+class Scenario:
+    """Device-resident scenario tables (nh_scenario_create)."""
+
+    def __init__(self, capacity, weights, nu: float, *, mode: int = NH_DISPERSAL_SHARED, lam: float = 1.0,
+                 dt: float = 1.0):
+        cap = np.ascontiguousarray(capacity, dtype=np.uint32)
+        if cap.ndim != 2:
+            raise ValueError("capacity must be a 2-D (H, W) array")
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        if w.ndim != 2 or w.shape[0] != w.shape[1] or w.shape[0] % 2 != 1:
+            raise ValueError("weights must be a square (2R+1, 2R+1) array")
+        hab = nh_habitat(cap.shape[1], cap.shape[0], cap.ctypes.data_as(C.POINTER(C.c_uint32)))
+        disp = nh_dispersal(w.shape[0] // 2, w.ctypes.data_as(C.POINTER(C.c_double)), mode)
+        par = nh_params(lam, dt)
+        h = C.c_void_p()
+        _check(_lib.nh_scenario_create(C.byref(hab), C.byref(disp), nu, C.byref(par), C.byref(h)),
+               "nh_scenario_create")
+        self._h = h
+        self.nu, self.mode, self.lam, self.dt = nu, mode, lam, dt
+        self.shape = cap.shape
+
+    @classmethod
+    def from_workload(cls, wl):
+        return cls(wl.capacity, wl.weights, wl.nu, mode=wl.mode, lam=wl.lam, dt=wl.dt)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def individuals(self) -> int:
+        return int(_lib.nh_scenario_individuals(self._h))
+
+    @property
+    def table_bytes(self) -> int:
+        return int(_lib.nh_scenario_table_bytes(self._h))
+
+    def footprint_bytes(self, n_samples: int) -> int:
+        return int(_lib.nh_scenario_footprint_bytes(self._h, n_samples))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.nh_scenario_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def simulate(scenario: Scenario, seed: int, samples) -> tuple[np.ndarray, int, dict]:
+    """Host-buffer simulate (nh_simulate): returns (species u64[n], richness, stats)."""
+    s = np.ascontiguousarray(samples, dtype=np.uint64)
+    out = np.zeros(len(s), dtype=np.uint64)
+    rich = C.c_uint64()
+    st = nh_stats()
+    _check(_lib.nh_simulate(scenario.handle, seed, s.ctypes.data_as(C.POINTER(C.c_uint64)), len(s),
+                            out.ctypes.data_as(C.POINTER(C.c_uint64)), C.byref(rich), C.byref(st)), "nh_simulate")
+    return out, int(rich.value), st.as_dict()
+
+
+def workspace_bytes(n_total: int, n_jobs: int) -> int:
+    return int(_lib.nh_workspace_bytes(n_total, n_jobs))
+
+
+def batch_run(jobs, workspace, config: nh_config | None = None, stream=None):
+    """nh_batch_run over device buffers.
+
+    jobs: list of (Scenario, seed, samples_tensor u64/int64 on the device, species_out tensor,
+    richness_out tensor or None).  workspace: a uint8 device tensor of at least
+    workspace_bytes(sum n, len(jobs)) bytes.  stream: a torch.cuda.Stream or None (current stream).
+    Returns the list of per-job stats dicts."""
+    import torch
+
+    arr = (nh_job * len(jobs))()
+    for k, (scn, seed, samples, out, rich) in enumerate(jobs):
+        arr[k].scenario = scn.handle
+        arr[k].seed = int(seed) & (2**64 - 1)
+        arr[k].d_sample_ids = samples.data_ptr() if samples.numel() else None
+        arr[k].n = samples.numel()
+        arr[k].d_species_out = out.data_ptr() if out.numel() else None
+        arr[k].d_richness_out = rich.data_ptr() if rich is not None else None
+    st = (nh_stats * len(jobs))()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(_lib.nh_batch_run(arr, len(jobs), workspace.data_ptr(), workspace.numel(),
+                             C.byref(config) if config is not None else None, st, C.c_void_p(s.cuda_stream)),
+           "nh_batch_run")
+    return [x.as_dict() for x in st]

@@ -1,0 +1,1306 @@
+// necsim_hip.hip - gfx950 kernels and C ABI of libnecsim_hip: the Independent
+// algorithm for neutral Moran biodiversity models (Langenstein 2021,
+// arXiv 2108.05815).  The public contract is include/necsim_hip.h.
+//
+// Paper sections this file implements (all in the chapter "The Declaration of
+// Independence" unless noted):
+//   "Environmental RNG Priming"         - counter-based hash keyed on (seed, location, time)
+//   "Aligning the RNGs of Colliding Individuals" and "Exponential inter-event
+//   Times" (memoryless sums)            - next_event_time()
+//   "Summary of the Independent Algorithm" - commit_event() and the lane loop
+//   implementation chapter, "Deduplicating Redundant Individuals" and the
+//   Water-Level algorithm               - horizon rounds + (location, next time) hash cull
+//   appendix "Sampling Probability Distributions" - 53-bit uniforms, inverse-transform Exp
+//   related work "Counter-based Pseudo-Random Number Generators" - Philox4x32-10
+//
+// Layout: one lane per lineage.  Lineage state is structure-of-arrays in HBM
+// (loc u32, next-event time f64, parent u32, species u64, job u32, events u32),
+// touched once per lineage per round; everything inside a round lives in
+// registers.  The round kernel is persistent over a fixed grid: lanes refill
+// from a device work queue with one wave-aggregated atomic, finished lineages
+// are either retired (speciation), merged (hash hit on (job, loc, t_next)) or
+// compacted into the next round's queue with ballot + mbcnt + one atomic per
+// wave.  Round kernels are replayed from captured HIP graphs while the host
+// polls a host-mapped status word written by the last workgroup of each round.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "necsim_hip.h"
+
+#define NH_API extern "C" __attribute__((visibility("default")))
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(NH_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
+                        __FILE__, __LINE__);                                                  \
+    } while (0)
+
+constexpr uint32_t kErrBadSample = 1u;
+constexpr uint32_t kErrRunaway = 2u;
+constexpr uint32_t kErrHashFull = 4u;
+constexpr uint32_t kMaxHorizons = 1024;
+
+// ---------------------------------------------------------------------------
+// Device data
+// ---------------------------------------------------------------------------
+// One simulate request, as the kernels see it.  Scenario constants first.
+struct JobDev {
+    uint64_t seed;
+    uint64_t nu_thresh;      // speciation iff (r0 >> 11) < ceil(nu * 2^53)
+    double inv_lambda;       // 1 / lambda
+    double dt, inv_dt;       // repriming interval (power of two) and its inverse
+    const uint4 *table;      // alias entries {thresh lo, thresh hi, packed offsets, 0}
+    const uint32_t *row_ptr; // per-deme mode: first entry of each cell (cells + 1)
+    const uint32_t *cap;     // capacity per cell
+    const uint64_t *prefix;  // capacity prefix (cells + 1)
+    const uint64_t *samples; // dense sample ids
+    unsigned long long *species_out;
+    unsigned long long *richness_out;
+    unsigned long long *rich_set; // open-addressing set of species ids, rich_mask + 1 slots
+    uint64_t n_individuals;
+    uint32_t W, H, cmax, R;
+    uint32_t mode, n_shared, cap_const, rich_mask;
+    uint32_t lin_base, n, start_round, pad;
+};
+
+// Per-job counters, written by the kernels.
+struct JobState {
+    uint32_t remaining;   // lineages not yet retired or merged
+    uint32_t flags;       // bit 0: a species id equal to the set's empty marker was seen
+    uint32_t done_round;
+    uint32_t pad;
+    unsigned long long rich_count;
+    unsigned long long events;
+    unsigned long long speciated;
+    unsigned long long merged;
+};
+
+// Run control block (device memory, inside the workspace).
+struct Ctl {
+    uint32_t round;      // round the next round kernel runs
+    uint32_t count[3];   // queue length of round r is count[r % 3]
+    uint32_t cursor[3];  // work-queue cursor of round r is cursor[r % 3]
+    uint32_t blocks_done;
+    uint32_t error;
+    uint32_t n_jobs;
+    uint32_t pad[6];
+};
+
+struct Lin {
+    uint32_t *loc;
+    double *t;
+    uint32_t *parent;
+    unsigned long long *species;
+    uint32_t *job;
+    uint32_t *events;
+    uint32_t *act[2];
+    unsigned long long *hash;
+    uint32_t hmask;
+};
+
+// Scenario constants a lane needs per event, loaded once per lineage.
+struct JobView {
+    uint32_t key0, key1;
+    uint64_t nu_thresh;
+    double inv_lambda, dt, inv_dt;
+    const uint4 *table;
+    const uint32_t *row_ptr;
+    const uint32_t *cap;
+    uint32_t W, H, cmax, R, mode, n_shared, cap_const;
+};
+
+__device__ __forceinline__ JobView load_view(const JobDev *__restrict__ J) {
+    JobView v;
+    v.key0 = (uint32_t)J->seed;
+    v.key1 = (uint32_t)(J->seed >> 32);
+    v.nu_thresh = J->nu_thresh;
+    v.inv_lambda = J->inv_lambda;
+    v.dt = J->dt;
+    v.inv_dt = J->inv_dt;
+    v.table = J->table;
+    v.row_ptr = J->row_ptr;
+    v.cap = J->cap;
+    v.W = J->W;
+    v.H = J->H;
+    v.cmax = J->cmax;
+    v.R = J->R;
+    v.mode = J->mode;
+    v.n_shared = J->n_shared;
+    v.cap_const = J->cap_const;
+    return v;
+}
+
+// Philox4x32-10 (Salmon et al. 2011): 10 rounds, two 32x32->64 products per
+// round; the Weyl key bump after the last round is never used.
+__device__ __forceinline__ void philox10(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3, uint32_t k0,
+                                         uint32_t k1) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// floor(r * n / 2^64) for n < 2^32, from two 32x32->64 products.
+__device__ __forceinline__ uint32_t mulhi_index(uint64_t r, uint32_t n) {
+    const uint64_t lo = (uint64_t)(uint32_t)r * n;
+    const uint64_t hi = (uint64_t)(uint32_t)(r >> 32) * n + (lo >> 32);
+    return (uint32_t)(hi >> 32);
+}
+
+// log(u) for u = ((r >> 11) + 1) * 2^-53 in (0, 1].  The decomposition
+// u = m * 2^e with m in [sqrt(1/2), sqrt(2)) is done on the integer q, then
+// log(m) = 2 atanh(s), s = (m - 1) / (m + 1), with the series
+// 2s (1 + z/3 + ... + z^10/21), z = s^2, and log(u) = e ln2 + log(m) with ln2
+// split into a 32-bit head and a tail.  Every floating-point operation is
+// spelled out (no contraction), so the result is the same bits on any
+// IEEE-754 binary64 machine that evaluates the same sequence.
+__device__ __forceinline__ double log_u53o(uint64_t r) {
+    const uint64_t q = (r >> 11) + 1ull;          // 1 .. 2^53
+    const int nb = 64 - __clzll((long long)q);     // bit length, 1 .. 54
+    const uint64_t frac = ((q << (64 - nb)) << 1) >> 12; // 52 bits after the leading one
+    int e = nb - 53;
+    uint64_t mbits;
+    if (frac < 0x6a09e667f3bcdull) {               // m = q / 2^nb < sqrt(1/2): use 2m
+        mbits = (1023ull << 52) | frac;
+        e -= 1;
+    } else {
+        mbits = (1022ull << 52) | frac;
+    }
+    const double m = __longlong_as_double((long long)mbits);
+    const double f = m - 1.0;
+    const double s = f / (2.0 + f);
+    const double z = s * s;
+    double p = 1.0 / 21.0;
+    p = __builtin_fma(p, z, 1.0 / 19.0);
+    p = __builtin_fma(p, z, 1.0 / 17.0);
+    p = __builtin_fma(p, z, 1.0 / 15.0);
+    p = __builtin_fma(p, z, 1.0 / 13.0);
+    p = __builtin_fma(p, z, 1.0 / 11.0);
+    p = __builtin_fma(p, z, 1.0 / 9.0);
+    p = __builtin_fma(p, z, 1.0 / 7.0);
+    p = __builtin_fma(p, z, 1.0 / 5.0);
+    p = __builtin_fma(p, z, 1.0 / 3.0);
+    p = p * z;
+    const double two_s = s + s;
+    const double log_m = __builtin_fma(two_s, p, two_s);
+    const double de = (double)e;
+    return __builtin_fma(de, 0x1.62e42fee00000p-1, __builtin_fma(de, 0x1.a39ef35793c76p-33, log_m));
+}
+
+// Next event time after t_last at location loc: interval k = [k dt, (k+1) dt)
+// is primed on (loc, k); Exp(lambda) draws are summed from k dt; a sum that
+// reaches (k+1) dt moves the search to interval k+1 (restarting at its start);
+// the first sum strictly beyond t_last is the answer.  Returns a negative
+// value (and flags the run) only if the search runs away, which needs a
+// broken scenario.
+__device__ __forceinline__ double next_event_time(const JobView &v, uint32_t loc, double t_last, uint32_t *err) {
+    uint64_t k = (uint64_t)floor(t_last * v.inv_dt);
+    double e = (double)k * v.dt;
+    double end = (double)(k + 1) * v.dt;
+    uint32_t j = 0;
+    uint64_t second = 0;
+    for (uint32_t guard = 0; guard < (1u << 24); ++guard) {
+        uint64_t r;
+        if ((j & 1u) == 0u) {
+            uint32_t c0 = loc, c1 = (uint32_t)k, c2 = (uint32_t)(k >> 32), c3 = j >> 1; // domain 0
+            philox10(c0, c1, c2, c3, v.key0, v.key1);
+            r = ((uint64_t)c1 << 32) | c0;
+            second = ((uint64_t)c3 << 32) | c2;
+        } else {
+            r = second;
+        }
+        const double x = (-log_u53o(r)) * v.inv_lambda;
+        e = e + x;
+        if (e >= end) {
+            k += 1;
+            e = (double)k * v.dt;
+            end = (double)(k + 1) * v.dt;
+            j = 0;
+            continue;
+        }
+        if (e > t_last) return e;
+        ++j;
+    }
+    atomicOr(err, kErrRunaway);
+    return -1.0;
+}
+
+// Lineage position in registers: torus coordinates, deme index and the packed
+// location loc = (y W + x) * cmax + i that keys the hash.
+struct Pos {
+    uint32_t x, y, i, loc;
+};
+
+__device__ __forceinline__ Pos pos_from_loc(const JobView &v, uint32_t loc) {
+    Pos p;
+    const uint32_t cell = loc / v.cmax;
+    p.i = loc - cell * v.cmax;
+    p.y = cell / v.W;
+    p.x = cell - p.y * v.W;
+    p.loc = loc;
+    return p;
+}
+
+// The event at (loc, t): draws r0, r1 (call 0) and r2, r3 (call 1) from the
+// event domain keyed on the bits of t.  Speciation iff U(r0) < nu, with the
+// species id from the species domain; otherwise the alias column from r1, the
+// alias coin from r2, the torus offset of the chosen entry, and the deme index
+// from r3.  Returns true on speciation.
+__device__ __forceinline__ bool commit_event(const JobView &v, Pos &p, double t, uint64_t &species) {
+    const uint64_t tb = (uint64_t)__double_as_longlong(t);
+    const uint32_t tlo = (uint32_t)tb, thi = (uint32_t)(tb >> 32);
+    uint32_t a0 = p.loc, a1 = tlo, a2 = thi, a3 = (1u << 30);
+    philox10(a0, a1, a2, a3, v.key0, v.key1);
+    const uint64_t r0 = ((uint64_t)a1 << 32) | a0;
+    const uint64_t r1 = ((uint64_t)a3 << 32) | a2;
+    if ((r0 >> 11) < v.nu_thresh) {
+        uint32_t s0 = p.loc, s1 = tlo, s2 = thi, s3 = (2u << 30);
+        philox10(s0, s1, s2, s3, v.key0, v.key1);
+        species = ((uint64_t)s1 << 32) | s0;
+        return true;
+    }
+    uint32_t b0 = p.loc, b1 = tlo, b2 = thi, b3 = (1u << 30) | 1u;
+    philox10(b0, b1, b2, b3, v.key0, v.key1);
+    const uint64_t r2 = ((uint64_t)b1 << 32) | b0;
+    const uint64_t r3 = ((uint64_t)b3 << 32) | b2;
+    uint32_t first, n;
+    if (v.mode == NH_DISPERSAL_SHARED) {
+        first = 0;
+        n = v.n_shared;
+    } else {
+        const uint32_t cell = p.y * v.W + p.x;
+        first = v.row_ptr[cell];
+        n = v.row_ptr[cell + 1] - first;
+    }
+    const uint32_t col = mulhi_index(r1, n);
+    const uint4 ent = v.table[first + col];
+    const uint64_t thresh = ((uint64_t)ent.y << 32) | ent.x;
+    const uint32_t off = ((r2 >> 11) < thresh) ? (ent.z & 0xFFFFu) : (ent.z >> 16);
+    int tx = (int)p.x + (int)(off & 0xFFu) - (int)v.R;
+    int ty = (int)p.y + (int)(off >> 8) - (int)v.R;
+    if (tx < 0) tx += (int)v.W;
+    else if (tx >= (int)v.W) tx -= (int)v.W;
+    if (ty < 0) ty += (int)v.H;
+    else if (ty >= (int)v.H) ty -= (int)v.H;
+    const uint32_t target = (uint32_t)ty * v.W + (uint32_t)tx;
+    const uint32_t capt = v.cap_const ? v.cap_const : v.cap[target];
+    p.x = (uint32_t)tx;
+    p.y = (uint32_t)ty;
+    p.i = mulhi_index(r3, capt);
+    p.loc = target * v.cmax + p.i;
+    return false;
+}
+
+__device__ __forceinline__ uint64_t mix_key(uint32_t loc, uint64_t tb, uint32_t job) {
+    uint64_t h = tb ^ ((uint64_t)loc * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)job << 40);
+    h ^= h >> 31;
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 29;
+    h *= 0x94D049BB133111EBull;
+    h ^= h >> 32;
+    return h;
+}
+
+// Cull table insert for round r: returns g if this lineage becomes the
+// representative of its (job, loc, t_next) state, else the representative's
+// id.  Slots hold (round << 32 | lineage); a slot from an older round is
+// empty.  The owner publishes its state before its CAS (release); readers
+// acquire before comparing the owner's state.
+__device__ __forceinline__ uint32_t cull_insert(const Lin &lin, uint32_t r, uint32_t g, uint32_t loc, uint64_t tb,
+                                                uint32_t job, uint32_t *err) {
+    uint32_t idx = (uint32_t)mix_key(loc, tb, job) & lin.hmask;
+    const unsigned long long mine = ((unsigned long long)r << 32) | g;
+    for (uint32_t probe = 0; probe <= lin.hmask; ++probe) {
+        unsigned long long cur = __hip_atomic_load(&lin.hash[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        while ((uint32_t)(cur >> 32) != r) {
+            if (__hip_atomic_compare_exchange_strong(&lin.hash[idx], &cur, mine, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                     __HIP_MEMORY_SCOPE_AGENT))
+                return g;
+        }
+        const uint32_t owner = (uint32_t)cur;
+        if (lin.loc[owner] == loc && (uint64_t)__double_as_longlong(lin.t[owner]) == tb && lin.job[owner] == job)
+            return owner;
+        idx = (idx + 1u) & lin.hmask;
+    }
+    atomicOr(err, kErrHashFull);
+    return g;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t wave_reserve(uint64_t mask, uint32_t *counter) {
+    // One atomic per wave for the lanes set in mask; each lane gets base + rank.
+    const uint32_t lane = lane_id();
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    uint32_t base = 0;
+    if ((int)lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    return base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long value) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+__global__ void k_setup(Ctl *ctl, JobState *js, const JobDev *jobs, uint32_t n_jobs, uint32_t first_round) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        ctl->round = first_round;
+        for (int k = 0; k < 3; ++k) {
+            ctl->count[k] = 0;
+            ctl->cursor[k] = 0;
+        }
+        ctl->blocks_done = 0;
+        ctl->error = 0;
+        ctl->n_jobs = n_jobs;
+    }
+    for (uint32_t j = t; j < n_jobs; j += gridDim.x * blockDim.x) {
+        js[j].remaining = jobs[j].n;
+        js[j].flags = 0;
+        js[j].done_round = 0;
+        js[j].rich_count = 0;
+        js[j].events = 0;
+        js[j].speciated = 0;
+        js[j].merged = 0;
+    }
+}
+
+// Binary search: the job whose lineage range holds g (jobs sorted by lin_base).
+__device__ __forceinline__ uint32_t job_of(const JobDev *jobs, uint32_t n_jobs, uint32_t g) {
+    uint32_t lo = 0, hi = n_jobs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (jobs[mid].lin_base <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Lineage init: dense sample id -> (cell, deme index) -> loc; first event time
+// from t = 0; append to the current round's queue.  An id >= N flags the run
+// and the lineage is left out of the queue.
+__global__ void k_init(Ctl *ctl, const JobDev *__restrict__ jobs, uint32_t n_jobs, Lin lin, uint32_t g_begin,
+                       uint32_t g_end) {
+    const uint32_t g = g_begin + blockIdx.x * blockDim.x + threadIdx.x;
+    bool push = false;
+    if (g < g_end) {
+        const uint32_t jb = job_of(jobs, n_jobs, g);
+        const JobDev *J = &jobs[jb];
+        const JobView v = load_view(J);
+        const uint64_t id = J->samples[g - J->lin_base];
+        uint32_t loc = 0;
+        double t = 0.0;
+        if (id >= J->n_individuals) {
+            atomicOr(&ctl->error, kErrBadSample);
+        } else {
+            const uint32_t cells = v.W * v.H;
+            uint32_t lo = 0, hi = cells; // last cell with prefix <= id
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (J->prefix[mid] <= id) lo = mid;
+                else hi = mid;
+            }
+            loc = lo * v.cmax + (uint32_t)(id - J->prefix[lo]);
+            t = next_event_time(v, loc, 0.0, &ctl->error);
+            push = t >= 0.0;
+        }
+        lin.loc[g] = loc;
+        lin.t[g] = t;
+        lin.parent[g] = g;
+        lin.species[g] = 0;
+        lin.job[g] = jb;
+        lin.events[g] = 0;
+    }
+    const uint64_t mask = __ballot(push);
+    if (mask) {
+        const uint32_t r = ctl->round;
+        const uint32_t slot = wave_reserve(mask, &ctl->count[r % 3]);
+        if (push) lin.act[r & 1][slot] = g;
+    }
+}
+
+// One horizon round over every queued lineage of every job.
+template <bool kSingleJob>
+__global__ __launch_bounds__(256) void k_round(Ctl *__restrict__ ctl, const JobDev *__restrict__ jobs,
+                                               JobState *__restrict__ js, Lin lin, const double *__restrict__ htab,
+                                               unsigned long long *status_host) {
+    const uint32_t r = ctl->round;
+    const uint32_t qin = r % 3, qout = (r + 1) % 3;
+    const uint32_t n_in = ctl->count[qin];
+    const uint32_t *__restrict__ act_in = lin.act[r & 1];
+    uint32_t *__restrict__ act_out = lin.act[(r + 1) & 1];
+    uint32_t *err = &ctl->error;
+
+    JobView v;
+    double w_single = 0.0;
+    if (kSingleJob) {
+        v = load_view(&jobs[0]);
+        const uint32_t lr = r - jobs[0].start_round;
+        w_single = htab[lr < kMaxHorizons ? lr : kMaxHorizons - 1];
+    }
+
+    bool has = false, queue_open = n_in > 0;
+    uint32_t g = 0, jb = 0, ev = 0;
+    Pos p = {0, 0, 0, 0};
+    double t = 0.0, horizon = 0.0;
+
+    while (true) {
+        // Refill idle lanes from the queue: one atomic per wave.
+        if (queue_open) {
+            const uint64_t need = __ballot(!has);
+            if (need) {
+                const uint32_t lane = lane_id();
+                const int leader = __ffsll((unsigned long long)need) - 1;
+                uint32_t base = 0;
+                if ((int)lane == leader) base = atomicAdd(&ctl->cursor[qin], (uint32_t)__popcll(need));
+                base = __shfl(base, leader, 64);
+                if (base + (uint32_t)__popcll(need) >= n_in) queue_open = false;
+                if (!has) {
+                    const uint32_t idx = base + (uint32_t)__popcll(need & ((1ull << lane) - 1ull));
+                    if (idx < n_in) {
+                        g = act_in[idx];
+                        if (!kSingleJob) {
+                            jb = lin.job[g];
+                            v = load_view(&jobs[jb]);
+                            const uint32_t lr = r - jobs[jb].start_round;
+                            horizon = htab[lr < kMaxHorizons ? lr : kMaxHorizons - 1];
+                        } else {
+                            horizon = w_single;
+                        }
+                        p = pos_from_loc(v, lin.loc[g]);
+                        t = lin.t[g];
+                        ev = 0;
+                        has = true;
+                    }
+                }
+            }
+        }
+        if (__ballot(has) == 0) break;
+
+        bool finish_live = false, finish_dead = false;
+        uint64_t sp = 0;
+        if (has) {
+            if (t > horizon) {
+                finish_live = true;
+            } else {
+                ++ev;
+                if (commit_event(v, p, t, sp)) {
+                    finish_dead = true;
+                } else {
+                    t = next_event_time(v, p.loc, t, err);
+                    if (t < 0.0) finish_dead = true; // runaway search (flagged)
+                    else if (t > horizon) finish_live = true;
+                }
+            }
+        }
+        if (finish_dead) {
+            lin.species[g] = sp;
+            lin.events[g] += ev;
+            has = false;
+        }
+        bool push = false;
+        if (finish_live) {
+            lin.loc[g] = p.loc;
+            lin.t[g] = t;
+            lin.events[g] += ev;
+            const uint32_t owner =
+                cull_insert(lin, r, g, p.loc, (uint64_t)__double_as_longlong(t), jb, err);
+            if (owner != g) {
+                lin.parent[g] = owner;
+            } else {
+                push = true;
+            }
+            has = false;
+        }
+        const uint64_t pm = __ballot(push);
+        if (pm) {
+            const uint32_t slot = wave_reserve(pm, &ctl->count[qout]);
+            if (push) act_out[slot] = g;
+        }
+    }
+
+    // Last workgroup of the round: advance the round and publish the status.
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t done = atomicAdd(&ctl->blocks_done, 1u);
+        if (done == gridDim.x - 1) {
+            __threadfence();
+            const uint32_t n_out = __hip_atomic_load(&ctl->count[qout], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            ctl->blocks_done = 0;
+            ctl->count[(r + 2) % 3] = 0;
+            ctl->cursor[qout] = 0;
+            ctl->round = r + 1;
+            const unsigned long long word =
+                ((unsigned long long)(r + 1) << 32) | n_out | ((unsigned long long)(ctl->error != 0) << 31);
+            __hip_atomic_store(status_host, word, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+}
+
+// Wave sum of a u64 over all 64 lanes.
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// Output: follow merge pointers to the representative, write species per
+// sample; representatives insert their species into the job's set.  Counters
+// are summed per wave when the whole wave belongs to one job.
+__global__ void k_resolve(const JobDev *__restrict__ jobs, uint32_t n_jobs, JobState *js, Lin lin, uint32_t g_end) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = g < g_end;
+    uint32_t jb = 0;
+    unsigned long long events = 0;
+    bool is_root = false;
+    if (valid) {
+        jb = lin.job[g];
+        const JobDev *J = &jobs[jb];
+        uint32_t x = g;
+        while (lin.parent[x] != x) x = lin.parent[x];
+        const unsigned long long sp = lin.species[x];
+        J->species_out[g - J->lin_base] = sp;
+        events = lin.events[g];
+        is_root = x == g;
+        if (is_root) {
+            if (sp == ~0ull) {
+                atomicOr(&js[jb].flags, 1u);
+            } else {
+                uint32_t idx = (uint32_t)sp & J->rich_mask;
+                for (uint32_t probe = 0; probe <= J->rich_mask; ++probe) {
+                    unsigned long long cur = ~0ull;
+                    if (__hip_atomic_compare_exchange_strong(&J->rich_set[idx], &cur, sp, __ATOMIC_RELAXED,
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        atomicAdd(&js[jb].rich_count, 1ull);
+                        break;
+                    }
+                    if (cur == sp) break;
+                    idx = (idx + 1u) & J->rich_mask;
+                }
+            }
+        }
+    }
+    const uint64_t vmask = __ballot(valid);
+    const int first = __ffsll((unsigned long long)vmask) - 1;
+    const uint32_t jb0 = __shfl(jb, first < 0 ? 0 : first, 64);
+    const bool uniform = __ballot(valid && jb != jb0) == 0;
+    if (uniform) {
+        const unsigned long long ev_sum = wave_sum(valid ? events : 0ull);
+        const unsigned long long roots = (unsigned long long)__popcll(__ballot(valid && is_root));
+        const unsigned long long n_valid = (unsigned long long)__popcll(vmask);
+        if (vmask && lane_id() == (uint32_t)first) {
+            atomicAdd(&js[jb0].events, ev_sum);
+            atomicAdd(&js[jb0].speciated, roots);
+            atomicAdd(&js[jb0].merged, n_valid - roots);
+        }
+    } else if (valid) {
+        atomicAdd(&js[jb].events, events);
+        atomicAdd(is_root ? &js[jb].speciated : &js[jb].merged, 1ull);
+    }
+}
+
+__global__ void k_finalize(const JobDev *__restrict__ jobs, uint32_t n_jobs, JobState *js) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_jobs) return;
+    const unsigned long long rich = js[j].rich_count + ((js[j].flags & 1u) ? 1ull : 0ull);
+    js[j].rich_count = rich;
+    if (jobs[j].richness_out) *jobs[j].richness_out = rich;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+inline uint64_t pow2_at_least(uint64_t x, uint64_t floor_value) {
+    uint64_t p = floor_value;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// ceil(p * 2^53) for p in [0, 1]: the integer threshold with
+// (r >> 11) < ceil(p 2^53)  <=>  (r >> 11) * 2^-53 < p.
+inline uint64_t u53_threshold(double p) { return (uint64_t)std::ceil(std::ldexp(p, 53)); }
+
+bool is_power_of_two(double x) {
+    int e;
+    const double m = std::frexp(x, &e);
+    return x > 0.0 && std::isfinite(x) && m == 0.5;
+}
+
+// Vose alias construction in a fixed order (the same steps as any conforming
+// implementation must take for bit-identical tables): p_i = (w_i n) / W with W
+// summed in index order; ascending scan into "small" (p < 1) and "large"
+// stacks; pop one of each (last pushed first), prob[s] = p_s, alias[s] = l,
+// p_l = (p_l + p_s) - 1, push l by its new value; leftovers keep prob 1.
+void vose(const double *w, uint32_t n, double *prob, uint32_t *alias, std::vector<double> &p,
+          std::vector<uint32_t> &small, std::vector<uint32_t> &large) {
+    double total = 0.0;
+    for (uint32_t i = 0; i < n; ++i) total = total + w[i];
+    p.resize(n);
+    small.resize(n);
+    large.resize(n);
+    uint32_t ns = 0, nl = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        p[i] = (w[i] * (double)n) / total;
+        if (p[i] < 1.0) small[ns++] = i;
+        else large[nl++] = i;
+    }
+    while (ns > 0 && nl > 0) {
+        const uint32_t s = small[--ns];
+        const uint32_t l = large[--nl];
+        prob[s] = p[s];
+        alias[s] = l;
+        p[l] = (p[l] + p[s]) - 1.0;
+        if (p[l] < 1.0) small[ns++] = l;
+        else large[nl++] = l;
+    }
+    while (nl > 0) {
+        const uint32_t l = large[--nl];
+        prob[l] = 1.0;
+        alias[l] = l;
+    }
+    while (ns > 0) {
+        const uint32_t s = small[--ns];
+        prob[s] = 1.0;
+        alias[s] = s;
+    }
+}
+
+// Alias table of one deme (cell < 0: the shared table) packed for the device:
+// x,y = threshold of the column, z = offsets of the column (low 16 bits) and of
+// its alias (high 16 bits), each as (dx + R) | (dy + R) << 8.
+struct TableBuilder {
+    uint32_t W, H, R, side;
+    const uint32_t *cap;
+    const double *weights;
+    std::vector<double> w, prob, p;
+    std::vector<uint32_t> kidx, alias, small, large;
+
+    uint32_t count(int64_t cell) const {
+        uint32_t n = 0;
+        for (uint32_t k = 0; k < side * side; ++k)
+            if (mass(cell, k) > 0.0) ++n;
+        return n;
+    }
+    double mass(int64_t cell, uint32_t k) const {
+        double wk = weights[k];
+        if (cell >= 0) {
+            const int64_t x = cell % W, y = cell / W;
+            const int64_t dx = (int64_t)(k % side) - R, dy = (int64_t)(k / side) - R;
+            const int64_t tx = ((x + dx) % (int64_t)W + W) % W;
+            const int64_t ty = ((y + dy) % (int64_t)H + H) % H;
+            wk = wk * (double)cap[ty * W + tx];
+        }
+        return wk;
+    }
+    uint32_t build(int64_t cell, uint4 *out) {
+        w.clear();
+        kidx.clear();
+        for (uint32_t k = 0; k < side * side; ++k) {
+            const double m = mass(cell, k);
+            if (m > 0.0) {
+                w.push_back(m);
+                kidx.push_back(k);
+            }
+        }
+        const uint32_t n = (uint32_t)w.size();
+        prob.resize(n);
+        alias.resize(n);
+        vose(w.data(), n, prob.data(), alias.data(), p, small, large);
+        auto pack = [&](uint32_t k) { return (k % side) | ((k / side) << 8); };
+        for (uint32_t c = 0; c < n; ++c) {
+            const uint64_t th = u53_threshold(prob[c]);
+            out[c] = make_uint4((uint32_t)th, (uint32_t)(th >> 32), pack(kidx[c]) | (pack(kidx[alias[c]]) << 16), 0u);
+        }
+        return n;
+    }
+};
+
+} // namespace
+
+struct nh_scenario {
+    int device = 0;
+    uint32_t W = 0, H = 0, R = 0, mode = 0, cmax = 0, cap_const = 0, n_shared = 0;
+    uint64_t cells = 0, N = 0, n_entries = 0;
+    double nu = 0, lambda = 1, dt = 1;
+    uint64_t nu_thresh = 0;
+    uint4 *d_table = nullptr;
+    uint32_t *d_row_ptr = nullptr;
+    uint32_t *d_cap = nullptr;
+    uint64_t *d_prefix = nullptr;
+    uint64_t table_bytes = 0;
+};
+
+namespace {
+
+void scenario_free(nh_scenario *s) {
+    if (!s) return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(s->device);
+    if (s->d_table) (void)hipFree(s->d_table);
+    if (s->d_row_ptr) (void)hipFree(s->d_row_ptr);
+    if (s->d_cap) (void)hipFree(s->d_cap);
+    if (s->d_prefix) (void)hipFree(s->d_prefix);
+    (void)hipSetDevice(prev);
+    delete s;
+}
+
+struct Workspace {
+    uint64_t off_ctl, off_jobs, off_js, off_htab, off_loc, off_t, off_parent, off_species, off_job, off_events,
+        off_act0, off_act1, off_hash, off_rich, total;
+    uint64_t hcap;
+};
+
+Workspace layout(uint64_t n_total, uint32_t n_jobs) {
+    Workspace w{};
+    const uint64_t N = std::max<uint64_t>(n_total, 1);
+    uint64_t o = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t at = o;
+        o = align_up(o + bytes, 256);
+        return at;
+    };
+    w.off_ctl = take(sizeof(Ctl));
+    w.off_jobs = take(sizeof(JobDev) * std::max<uint32_t>(n_jobs, 1));
+    w.off_js = take(sizeof(JobState) * std::max<uint32_t>(n_jobs, 1));
+    w.off_htab = take(sizeof(double) * kMaxHorizons);
+    w.off_loc = take(4 * N);
+    w.off_t = take(8 * N);
+    w.off_parent = take(4 * N);
+    w.off_species = take(8 * N);
+    w.off_job = take(4 * N);
+    w.off_events = take(4 * N);
+    w.off_act0 = take(4 * N);
+    w.off_act1 = take(4 * N);
+    w.hcap = pow2_at_least(2 * N, 1024);
+    w.off_hash = take(8 * w.hcap);
+    w.off_rich = take(8 * (4 * N + 64ull * std::max<uint32_t>(n_jobs, 1)));
+    w.total = o;
+    return w;
+}
+
+struct PinnedStatus {
+    unsigned long long *host = nullptr;
+    unsigned long long *dev = nullptr;
+};
+
+int pinned_status(PinnedStatus &out) {
+    thread_local PinnedStatus ps;
+    if (!ps.host) {
+        void *h = nullptr;
+        HIP_TRY(hipHostMalloc(&h, 256, hipHostMallocMapped | hipHostMallocPortable | hipHostMallocCoherent));
+        void *d = nullptr;
+        HIP_TRY(hipHostGetDevicePointer(&d, h, 0));
+        ps.host = (unsigned long long *)h;
+        ps.dev = (unsigned long long *)d;
+    }
+    out = ps;
+    return NH_OK;
+}
+
+void fill_config(const nh_config *in, nh_config &c) {
+    c = nh_config{};
+    if (in) c = *in;
+    if (!(c.horizon0 > 0)) c.horizon0 = 0.5;
+    if (!(c.horizon_growth > 1.0)) c.horizon_growth = 1.25;
+    if (!(c.horizon_step_max > 0)) c.horizon_step_max = 4096.0;
+    if (c.block_size == 0) c.block_size = 256;
+    if (c.blocks_per_cu == 0) c.blocks_per_cu = 4;
+    if (c.rounds_per_graph == 0) c.rounds_per_graph = 8;
+    if (!(c.timeout_s > 0)) c.timeout_s = 600.0;
+}
+
+std::vector<double> horizon_table(const nh_config &c) {
+    std::vector<double> h(kMaxHorizons, 0.0);
+    h[0] = 0.0;
+    h[1] = c.horizon0;
+    for (uint32_t i = 2; i < kMaxHorizons; ++i)
+        h[i] = h[i - 1] + std::min(c.horizon_step_max, h[i - 1] * (c.horizon_growth - 1.0));
+    return h;
+}
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+NH_API const char *nh_last_error(void) { return g_last_error.c_str(); }
+
+NH_API const char *nh_version(void) { return "libnecsim_hip 0.1 (gfx950)"; }
+
+NH_API int nh_scenario_create(const nh_habitat *habitat, const nh_dispersal *dispersal, double nu,
+                              const nh_params *params, nh_scenario **out) {
+    if (!out) return fail(NH_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!habitat || !dispersal || !habitat->h_capacity || !dispersal->h_weights)
+        return fail(NH_EINVAL, "NULL habitat or dispersal");
+    const uint32_t W = habitat->width, H = habitat->height, R = dispersal->radius;
+    if (W == 0 || H == 0) return fail(NH_EINVAL, "empty habitat");
+    if (dispersal->mode > 1) return fail(NH_EINVAL, "unknown dispersal mode %u", dispersal->mode);
+    if (R > 127 || 2ull * R + 1 > W || 2ull * R + 1 > H)
+        return fail(NH_EINVAL, "kernel side 2R+1 = %llu exceeds the habitat or 255", 2ull * R + 1);
+    if (!(nu > 0.0 && nu <= 1.0)) return fail(NH_EINVAL, "nu must lie in (0, 1]");
+    const double lambda = params ? params->lambda : 1.0;
+    const double dt = params ? params->delta_t : 1.0;
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(NH_EINVAL, "lambda must be positive and finite");
+    if (!is_power_of_two(dt)) return fail(NH_EINVAL, "delta_t must be a positive power of two");
+    if (lambda * dt > 1048576.0) return fail(NH_EINVAL, "lambda * delta_t must not exceed 2^20");
+    const uint32_t side = 2 * R + 1;
+    for (uint32_t k = 0; k < side * side; ++k) {
+        const double w = dispersal->h_weights[k];
+        if (!(w >= 0.0) || !std::isfinite(w)) return fail(NH_EINVAL, "weight %u is negative or not finite", k);
+    }
+    const uint64_t cells = (uint64_t)W * H;
+    const uint32_t *cap = habitat->h_capacity;
+    std::vector<uint64_t> prefix(cells + 1);
+    uint64_t acc = 0;
+    uint32_t cmax = 0;
+    bool constant = true;
+    for (uint64_t c = 0; c < cells; ++c) {
+        prefix[c] = acc;
+        acc += cap[c];
+        cmax = std::max(cmax, cap[c]);
+        if (cap[c] != cap[0]) constant = false;
+        if (dispersal->mode == NH_DISPERSAL_SHARED && cap[c] == 0)
+            return fail(NH_EINVAL, "the shared dispersal mode needs every deme habitable (cell %llu)",
+                        (unsigned long long)c);
+    }
+    prefix[cells] = acc;
+    if (acc == 0) return fail(NH_EINVAL, "no habitable deme");
+    if (cells * (uint64_t)cmax >= (1ull << 32)) return fail(NH_EINVAL, "width*height*max capacity must be < 2^32");
+
+    nh_scenario *s = new nh_scenario();
+    (void)hipGetDevice(&s->device);
+    s->W = W;
+    s->H = H;
+    s->R = R;
+    s->mode = dispersal->mode;
+    s->cmax = cmax;
+    s->cap_const = constant ? cap[0] : 0;
+    s->cells = cells;
+    s->N = acc;
+    s->nu = nu;
+    s->lambda = lambda;
+    s->dt = dt;
+    s->nu_thresh = u53_threshold(nu);
+
+    TableBuilder tb;
+    tb.W = W;
+    tb.H = H;
+    tb.R = R;
+    tb.side = side;
+    tb.cap = cap;
+    tb.weights = dispersal->h_weights;
+
+    auto bail = [&](int code) {
+        scenario_free(s);
+        return code;
+    };
+
+    if (s->mode == NH_DISPERSAL_SHARED) {
+        const uint32_t n = tb.count(-1);
+        if (n == 0) return bail(fail(NH_EINVAL, "all dispersal weights are zero"));
+        std::vector<uint4> host(n);
+        tb.build(-1, host.data());
+        s->n_shared = n;
+        s->n_entries = n;
+        if (hipMalloc(&s->d_table, sizeof(uint4) * n) != hipSuccess)
+            return bail(fail(NH_ENOMEM, "device table allocation failed"));
+        if (hipMemcpy(s->d_table, host.data(), sizeof(uint4) * n, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(NH_EDEVICE, "table upload failed"));
+    } else {
+        // Per-deme tables in CSR order, built by host threads in chunks and
+        // uploaded through a staging buffer.
+        std::vector<uint32_t> counts(cells, 0);
+        const unsigned nthreads = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+        {
+            std::vector<std::thread> pool;
+            std::atomic<bool> bad{false};
+            for (unsigned tid = 0; tid < nthreads; ++tid) {
+                pool.emplace_back([&, tid] {
+                    for (uint64_t c = tid; c < cells; c += nthreads) {
+                        if (cap[c] == 0) continue;
+                        counts[c] = tb.count((int64_t)c);
+                        if (counts[c] == 0) bad = true;
+                    }
+                });
+            }
+            for (auto &th : pool) th.join();
+            if (bad) return bail(fail(NH_EINVAL, "a habitable deme has no habitable mass in its dispersal kernel"));
+        }
+        std::vector<uint32_t> row(cells + 1);
+        uint64_t total = 0;
+        for (uint64_t c = 0; c < cells; ++c) {
+            row[c] = (uint32_t)total;
+            total += counts[c];
+            if (total >= (1ull << 32)) return bail(fail(NH_EINVAL, "more than 2^32 per-deme table entries"));
+        }
+        row[cells] = (uint32_t)total;
+        s->n_entries = total;
+        if (hipMalloc(&s->d_table, sizeof(uint4) * std::max<uint64_t>(total, 1)) != hipSuccess)
+            return bail(fail(NH_ENOMEM, "device table allocation (%llu entries) failed", (unsigned long long)total));
+        if (hipMalloc(&s->d_row_ptr, sizeof(uint32_t) * (cells + 1)) != hipSuccess)
+            return bail(fail(NH_ENOMEM, "row pointer allocation failed"));
+        if (hipMemcpy(s->d_row_ptr, row.data(), sizeof(uint32_t) * (cells + 1), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(NH_EDEVICE, "row pointer upload failed"));
+        const uint64_t chunk_entries = 1ull << 24; // 256 MB staging
+        std::vector<uint4> stage((size_t)std::min<uint64_t>(chunk_entries + side * side, total + 1));
+        uint64_t c0 = 0;
+        while (c0 < cells) {
+            uint64_t c1 = c0;
+            while (c1 < cells && (uint64_t)row[c1 + 1] - row[c0] <= chunk_entries) ++c1;
+            if (c1 == c0) c1 = c0 + 1;
+            const uint64_t base = row[c0];
+            std::vector<std::thread> pool;
+            for (unsigned tid = 0; tid < nthreads; ++tid) {
+                pool.emplace_back([&, tid] {
+                    TableBuilder local = tb;
+                    for (uint64_t c = c0 + tid; c < c1; c += nthreads)
+                        if (counts[c]) local.build((int64_t)c, stage.data() + (row[c] - base));
+                });
+            }
+            for (auto &th : pool) th.join();
+            const uint64_t n = (uint64_t)row[c1] - base;
+            if (n && hipMemcpy(s->d_table + base, stage.data(), sizeof(uint4) * n, hipMemcpyHostToDevice) != hipSuccess)
+                return bail(fail(NH_EDEVICE, "table upload failed"));
+            c0 = c1;
+        }
+    }
+    if (hipMalloc(&s->d_cap, sizeof(uint32_t) * cells) != hipSuccess ||
+        hipMalloc(&s->d_prefix, sizeof(uint64_t) * (cells + 1)) != hipSuccess)
+        return bail(fail(NH_ENOMEM, "capacity allocation failed"));
+    if (hipMemcpy(s->d_cap, cap, sizeof(uint32_t) * cells, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->d_prefix, prefix.data(), sizeof(uint64_t) * (cells + 1), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(NH_EDEVICE, "capacity upload failed"));
+    s->table_bytes = sizeof(uint4) * s->n_entries + (s->d_row_ptr ? 4 * (cells + 1) : 0) + 4 * cells + 8 * (cells + 1);
+    *out = s;
+    return NH_OK;
+}
+
+NH_API void nh_scenario_destroy(nh_scenario *s) { scenario_free(s); }
+
+NH_API uint64_t nh_scenario_individuals(const nh_scenario *s) { return s ? s->N : 0; }
+
+NH_API uint64_t nh_scenario_table_bytes(const nh_scenario *s) { return s ? s->table_bytes : 0; }
+
+NH_API uint64_t nh_workspace_bytes(uint64_t n_total, uint32_t n_jobs) { return layout(n_total, n_jobs).total; }
+
+NH_API uint64_t nh_scenario_footprint_bytes(const nh_scenario *s, uint64_t n_samples) {
+    return (s ? s->table_bytes : 0) + layout(n_samples, 1).total;
+}
+
+NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint64_t workspace_bytes,
+                        const nh_config *cfg_in, nh_stats *stats, void *stream_ptr) {
+    using clock = std::chrono::steady_clock;
+    hipStream_t stream = (hipStream_t)stream_ptr;
+    if (n_jobs == 0) return NH_OK;
+    if (!jobs) return fail(NH_EINVAL, "jobs is NULL");
+    nh_config cfg;
+    fill_config(cfg_in, cfg);
+    if (cfg.block_size % 64 != 0 || cfg.block_size > 256 || cfg.rounds_per_graph > 256)
+        return fail(NH_EINVAL, "block_size must be a multiple of 64 up to 256, rounds_per_graph <= 256");
+    uint64_t n_total = 0;
+    for (uint32_t j = 0; j < n_jobs; ++j) {
+        const nh_job &jb = jobs[j];
+        if (!jb.scenario) return fail(NH_EINVAL, "job %u has no scenario", j);
+        if (jb.n > 0 && (!jb.d_sample_ids || !jb.d_species_out))
+            return fail(NH_EINVAL, "job %u has NULL sample or output buffers", j);
+        n_total += jb.n;
+    }
+    if (n_total >= (1ull << 31)) return fail(NH_EINVAL, "more than 2^31 - 1 samples in one batch");
+    const Workspace L = layout(n_total, n_jobs);
+    if (!d_workspace || workspace_bytes < L.total)
+        return fail(NH_ENOMEM, "workspace of %llu bytes is smaller than the %llu needed",
+                    (unsigned long long)workspace_bytes, (unsigned long long)L.total);
+    if (((uintptr_t)d_workspace & 255) != 0) return fail(NH_EINVAL, "workspace must be 256-byte aligned");
+
+    char *ws = (char *)d_workspace;
+    Ctl *ctl = (Ctl *)(ws + L.off_ctl);
+    JobDev *d_jobs = (JobDev *)(ws + L.off_jobs);
+    JobState *d_js = (JobState *)(ws + L.off_js);
+    double *d_htab = (double *)(ws + L.off_htab);
+    Lin lin;
+    lin.loc = (uint32_t *)(ws + L.off_loc);
+    lin.t = (double *)(ws + L.off_t);
+    lin.parent = (uint32_t *)(ws + L.off_parent);
+    lin.species = (unsigned long long *)(ws + L.off_species);
+    lin.job = (uint32_t *)(ws + L.off_job);
+    lin.events = (uint32_t *)(ws + L.off_events);
+    lin.act[0] = (uint32_t *)(ws + L.off_act0);
+    lin.act[1] = (uint32_t *)(ws + L.off_act1);
+    lin.hash = (unsigned long long *)(ws + L.off_hash);
+    lin.hmask = (uint32_t)(L.hcap - 1);
+    unsigned long long *rich = (unsigned long long *)(ws + L.off_rich);
+
+    // Job descriptors.
+    std::vector<JobDev> hj(n_jobs);
+    uint64_t base = 0, rich_off = 0;
+    bool all_same_scenario = true;
+    for (uint32_t j = 0; j < n_jobs; ++j) {
+        const nh_scenario *s = jobs[j].scenario;
+        if (s != jobs[0].scenario) all_same_scenario = false;
+        JobDev &d = hj[j];
+        std::memset(&d, 0, sizeof d);
+        d.seed = jobs[j].seed;
+        d.nu_thresh = s->nu_thresh;
+        d.inv_lambda = 1.0 / s->lambda;
+        d.dt = s->dt;
+        d.inv_dt = 1.0 / s->dt;
+        d.table = s->d_table;
+        d.row_ptr = s->d_row_ptr;
+        d.cap = s->d_cap;
+        d.prefix = s->d_prefix;
+        d.samples = jobs[j].d_sample_ids;
+        d.species_out = (unsigned long long *)jobs[j].d_species_out;
+        d.richness_out = (unsigned long long *)jobs[j].d_richness_out;
+        const uint64_t slots = pow2_at_least(2 * jobs[j].n, 64);
+        d.rich_set = rich + rich_off;
+        d.rich_mask = (uint32_t)(slots - 1);
+        rich_off += slots;
+        d.n_individuals = s->N;
+        d.W = s->W;
+        d.H = s->H;
+        d.cmax = s->cmax;
+        d.R = s->R;
+        d.mode = s->mode;
+        d.n_shared = s->n_shared;
+        d.cap_const = s->cap_const;
+        d.lin_base = (uint32_t)base;
+        d.n = (uint32_t)jobs[j].n;
+        d.start_round = 0;
+        base += jobs[j].n;
+    }
+    (void)all_same_scenario;
+    const std::vector<double> htab = horizon_table(cfg);
+
+    PinnedStatus st;
+    if (int rc = pinned_status(st)) return rc;
+
+    hipEvent_t ev0, ev1;
+    HIP_TRY(hipEventCreate(&ev0));
+    HIP_TRY(hipEventCreate(&ev1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } evg{ev0, ev1};
+
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int n_cu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+
+    HIP_TRY(hipEventRecord(ev0, stream));
+    HIP_TRY(hipMemcpyAsync(d_jobs, hj.data(), sizeof(JobDev) * n_jobs, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(d_htab, htab.data(), sizeof(double) * kMaxHorizons, hipMemcpyHostToDevice, stream));
+    const uint32_t first_round = 1;
+    k_setup<<<std::max<uint32_t>(1, (n_jobs + 255) / 256), 256, 0, stream>>>(ctl, d_js, d_jobs, n_jobs, first_round);
+    k_fill_u64<<<1024, 256, 0, stream>>>(lin.hash, L.hcap, 0ull);
+    if (rich_off) k_fill_u64<<<1024, 256, 0, stream>>>(rich, rich_off, ~0ull);
+    if (n_total) {
+        const uint32_t blocks = (uint32_t)((n_total + 255) / 256);
+        k_init<<<blocks, 256, 0, stream>>>(ctl, d_jobs, n_jobs, lin, 0, (uint32_t)n_total);
+    }
+    HIP_TRY(hipGetLastError());
+    // The status word: round 0 and "not finished" until the first round kernel reports.
+    __atomic_store_n(st.host, (unsigned long long)1, __ATOMIC_SEQ_CST);
+
+    // Round kernels: replayed from a captured graph of cfg.rounds_per_graph launches.
+    const uint32_t grid = (uint32_t)std::max(1, n_cu) * cfg.blocks_per_cu;
+    const bool single = n_jobs == 1;
+    auto launch_round = [&](hipStream_t s) {
+        if (single)
+            k_round<true><<<grid, cfg.block_size, 0, s>>>(ctl, d_jobs, d_js, lin, d_htab, st.dev);
+        else
+            k_round<false><<<grid, cfg.block_size, 0, s>>>(ctl, d_jobs, d_js, lin, d_htab, st.dev);
+    };
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    struct GraphGuard {
+        hipGraph_t &g;
+        hipGraphExec_t &e;
+        ~GraphGuard() {
+            if (e) (void)hipGraphExecDestroy(e);
+            if (g) (void)hipGraphDestroy(g);
+        }
+    } gg{graph, exec};
+    bool use_graph = cfg.rounds_per_graph > 1;
+    if (use_graph && n_total) {
+        hipStream_t cap_stream;
+        HIP_TRY(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (uint32_t k = 0; k < cfg.rounds_per_graph; ++k) launch_round(cap_stream);
+            e = hipStreamEndCapture(cap_stream, &graph);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipStreamDestroy(cap_stream);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            use_graph = false;
+        }
+    }
+    const uint32_t per_launch = use_graph ? cfg.rounds_per_graph : 1;
+    uint64_t rounds_enqueued = 0;
+    auto enqueue = [&]() -> int {
+        if (use_graph) HIP_TRY(hipGraphLaunch(exec, stream));
+        else launch_round(stream);
+        HIP_TRY(hipGetLastError());
+        rounds_enqueued += per_launch;
+        return NH_OK;
+    };
+    const auto t_start = clock::now();
+    uint32_t final_round = 0;
+    if (n_total) {
+        // Keep two launches in flight; stop when a round reports an empty queue.
+        if (int rc = enqueue()) return rc;
+        if (int rc = enqueue()) return rc;
+        uint64_t spins = 0;
+        for (;;) {
+            const unsigned long long word = __atomic_load_n(st.host, __ATOMIC_ACQUIRE);
+            const uint32_t next_round = (uint32_t)(word >> 32);
+            const uint32_t live = (uint32_t)(word & 0x7FFFFFFFu);
+            const bool errflag = (word >> 31) & 1u;
+            if (next_round >= 2 && (live == 0 || errflag)) {
+                final_round = next_round - 1;
+                break;
+            }
+            const uint64_t completed = next_round >= 1 ? next_round - 1 : 0;
+            if (rounds_enqueued < completed + 2 * per_launch) {
+                if (int rc = enqueue()) return rc;
+                continue;
+            }
+            if ((++spins & 255) == 0) {
+                const double el = std::chrono::duration<double>(clock::now() - t_start).count();
+                if (el > cfg.timeout_s) {
+                    (void)hipStreamSynchronize(stream);
+                    return fail(NH_ETIMEOUT, "run exceeded %.1f s (round %u, %u lineages live)", cfg.timeout_s,
+                                next_round, live);
+                }
+                std::this_thread::yield();
+            }
+        }
+        const uint32_t blocks = (uint32_t)((n_total + 255) / 256);
+        k_resolve<<<blocks, 256, 0, stream>>>(d_jobs, n_jobs, d_js, lin, (uint32_t)n_total);
+    }
+    k_finalize<<<(n_jobs + 255) / 256, 256, 0, stream>>>(d_jobs, n_jobs, d_js);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(ev1, stream));
+    std::vector<JobState> hs(n_jobs);
+    Ctl hctl;
+    HIP_TRY(hipMemcpyAsync(hs.data(), d_js, sizeof(JobState) * n_jobs, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(&hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (hctl.error & kErrBadSample) return fail(NH_EINVAL, "a sample id is not below the number of individuals");
+    if (hctl.error) return fail(NH_EDEVICE, "kernel reported error flags 0x%x", hctl.error);
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+    if (stats) {
+        for (uint32_t j = 0; j < n_jobs; ++j) {
+            stats[j].events = hs[j].events;
+            stats[j].lineages = jobs[j].n;
+            stats[j].speciated = hs[j].speciated;
+            stats[j].merged = hs[j].merged;
+            stats[j].rounds = final_round;
+            stats[j].richness = hs[j].rich_count;
+            stats[j].device_ms = ms;
+        }
+    }
+    return NH_OK;
+}
+
+NH_API int nh_simulate_device(const nh_scenario *scenario, uint64_t seed, const uint64_t *d_sample_ids, uint64_t n,
+                              uint64_t *d_species_out, uint64_t *d_richness_out, const nh_config *cfg,
+                              nh_stats *stats, void *stream_ptr) {
+    if (!scenario) return fail(NH_EINVAL, "scenario is NULL");
+    hipStream_t stream = (hipStream_t)stream_ptr;
+    nh_job job{scenario, seed, d_sample_ids, n, d_species_out, d_richness_out};
+    const uint64_t bytes = nh_workspace_bytes(n, 1);
+    void *ws = nullptr;
+    HIP_TRY(hipMallocAsync(&ws, bytes, stream));
+    const int rc = nh_batch_run(&job, 1, ws, bytes, cfg, stats, stream_ptr);
+    (void)hipFreeAsync(ws, stream);
+    return rc;
+}
+
+NH_API int nh_simulate(const nh_scenario *scenario, uint64_t seed, const uint64_t *h_sample_ids, uint64_t n,
+                       uint64_t *h_species_out, uint64_t *h_richness_out, nh_stats *stats) {
+    if (!scenario) return fail(NH_EINVAL, "scenario is NULL");
+    if (n > 0 && (!h_sample_ids || !h_species_out)) return fail(NH_EINVAL, "NULL sample or output buffer");
+    for (uint64_t q = 0; q < n; ++q)
+        if (h_sample_ids[q] >= scenario->N) return fail(NH_EINVAL, "sample id %llu out of range", (unsigned long long)h_sample_ids[q]);
+    uint64_t *d_s = nullptr, *d_o = nullptr, *d_r = nullptr;
+    const uint64_t m = std::max<uint64_t>(n, 1);
+    HIP_TRY(hipMalloc(&d_s, 8 * m));
+    struct Free {
+        void *p;
+        ~Free() {
+            if (p) (void)hipFree(p);
+        }
+    } f1{d_s};
+    HIP_TRY(hipMalloc(&d_o, 8 * m));
+    Free f2{d_o};
+    HIP_TRY(hipMalloc(&d_r, 8));
+    Free f3{d_r};
+    if (n) HIP_TRY(hipMemcpy(d_s, h_sample_ids, 8 * n, hipMemcpyHostToDevice));
+    const uint64_t bytes = nh_workspace_bytes(n, 1);
+    void *ws = nullptr;
+    HIP_TRY(hipMalloc(&ws, bytes));
+    Free f4{ws};
+    nh_job job{scenario, seed, d_s, n, d_o, d_r};
+    const int rc = nh_batch_run(&job, 1, ws, bytes, nullptr, stats, nullptr);
+    if (rc != NH_OK) return rc;
+    if (n) HIP_TRY(hipMemcpy(h_species_out, d_o, 8 * n, hipMemcpyDeviceToHost));
+    uint64_t rich = 0;
+    HIP_TRY(hipMemcpy(&rich, d_r, 8, hipMemcpyDeviceToHost));
+    if (h_richness_out) *h_richness_out = rich;
+    return NH_OK;
+}
