@@ -1,0 +1,151 @@
+#!/usr/bin/env python3
+"""Benchmark of the Independent-algorithm hot path on one MI355X.
+
+A step is one complete simulate of the plain form on the spatially explicit
+workload (256 x 256 torus, one individual per cell, Gaussian sigma = 2 on a
+21 x 21 kernel, nu = 1e-3, all 65,536 individuals sampled): lineage init,
+horizon rounds (event sampling, dispersal, culling, compaction), output and
+richness -- every kernel of the path, on inputs already resident in HBM.  The
+scenario tables are built once (they are the scenario, like model weights);
+each step uses its own seed.
+
+Prints one JSON line: lineage events/s (value), individuals/s, the round
+kernel's VALU roofline fraction (HIP events on the library's stream), and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "lineage events/s & individuals/s vs CPU oracle; serve p50/p99 latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="bound on the oracle baseline's CPU time")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_round_c2_traffic.json"),
+                    help="HBM bytes per round launch from rocprofv3 FETCH_SIZE/WRITE_SIZE runs")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, budget_s: float) -> dict:
+    """The oracle's culled form on whole seeds of the same workload until the budget is spent."""
+    import oracle
+    sc = oracle.Scenario(wl.capacity, wl.weights, wl.nu, mode=wl.mode)
+    events = 0
+    runs = 0
+    t0 = time.perf_counter()
+    while True:
+        _, ev, _ = sc.simulate_culled(42 + runs, wl.samples, 1.0)
+        events += ev
+        runs += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": events / el, "unit": "lineage events/s", "cores": 1, "kind": "oracle",
+            "individuals_per_s": runs * len(wl.samples) / el,
+            "sample": f"{runs} whole seeds (42..{41 + runs}) of the same 65,536-lineage workload, "
+                      f"single-threaded culled oracle (horizon step 1.0), {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method shards by samples with no "
+              "communication, and multi-GPU runs are not part of this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2108_05815_amd import binding as B
+    from paper_2108_05815_amd import roofline as RL
+    from paper_2108_05815_amd import workloads as W
+
+    wl = W.config2()
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    scn = B.Scenario.from_workload(wl)
+    create_ms = (time.perf_counter() - t0) * 1e3
+    n = len(wl.samples)
+    samples = torch.from_numpy(wl.samples.astype(np.int64)).to(dev)
+    out = torch.empty(n, dtype=torch.int64, device=dev)
+    rich = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(B.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
+    cfg = B.make_config(event_timing=1)
+    stream = torch.cuda.current_stream()
+
+    for k in range(args.warmup):
+        B.batch_run([(scn, 1000 + k, samples, out, rich)], ws, cfg, stream)
+    torch.cuda.synchronize()
+    totals = dict(events=0, philox_calls=0, exp_draws=0, round_kernels=0, round_kernel_ms=0.0, richness=0)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        st = B.batch_run([(scn, 42 + k, samples, out, rich)], ws, cfg, stream)[0]
+        for key in totals:
+            totals[key] += st[key]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    events_per_s = totals["events"] / elapsed
+    ops = RL.algorithmic_ops(totals["philox_calls"], totals["exp_draws"], totals["events"])
+    round_s = totals["round_kernel_ms"] / 1e3
+    achieved = ops / round_s / 1e12 if round_s > 0 else 0.0
+    peak = RL.PEAK_LANE_OPS / 1e12
+    traffic = None
+    if os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            tr = json.load(f)
+        traffic = tr.get("bytes_per_launch")
+    line = {
+        "metric": METRIC,
+        "value": events_per_s,
+        "unit": "lineage events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32/f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "form": "plain (one scenario per run)", "lineages": n, "torus": "256x256",
+                   "capacity": 1, "sigma": 2.0, "kernel": "21x21", "nu": wl.nu, "lambda": 1.0, "delta_t": 1.0,
+                   "seeds": f"42..{41 + args.steps}"},
+        "individuals_per_s": args.steps * n / elapsed,
+        "events_per_step": totals["events"] / args.steps,
+        "mean_richness": totals["richness"] / args.steps,
+        "scenario_create_ms": create_ms,
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_round (horizon round: event sampling, dispersal, cull, compaction)",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "T lane-ops/s",
+            "frac": achieved / peak,
+            "traffic": traffic,
+            "avg_launch_us": totals["round_kernel_ms"] * 1e3 / max(1, totals["round_kernels"]),
+            "launches": totals["round_kernels"],
+            "ops_per_launch": ops / max(1, totals["round_kernels"]),
+            "philox_per_event": totals["philox_calls"] / max(1, totals["events"]),
+            "draws_per_event": totals["exp_draws"] / max(1, totals["events"]),
+        },
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

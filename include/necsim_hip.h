@@ -92,8 +92,10 @@ typedef struct {
     double horizon_step_max; /* cap on one round's horizon advance, default 4096 */
     uint32_t block_size;  /* threads per workgroup of the round kernel (64..1024), default 256 */
     uint32_t blocks_per_cu; /* workgroups per compute unit, default 4 */
-    uint32_t rounds_per_graph; /* round kernels per captured graph, default 8 */
-    uint32_t table_in_lds; /* 1: stage a shared dispersal table in LDS when it fits, default 1 */
+    uint32_t rounds_per_graph; /* round kernels per captured graph (1 = plain launches), default 8 */
+    uint32_t event_timing; /* 1: bracket every round launch with HIP events (fills round_kernel_ms) */
+    uint32_t coop_max;    /* queues shorter than this many lineages run 8 lanes per lineage; default
+                             (0): a launch's lane count / 8 + 1; 1 keeps one lane per lineage always */
     double timeout_s;     /* wall-clock limit of one run, default 600 */
 } nh_config;
 
@@ -106,6 +108,11 @@ typedef struct {
     uint64_t rounds;    /* horizon rounds the job took part in */
     uint64_t richness;
     double device_ms;   /* stream time of the whole run (same for every job of a batch) */
+    /* Totals of the whole run (the same for every job of a batch): */
+    uint64_t philox_calls;   /* Philox4x32-10 blocks evaluated */
+    uint64_t exp_draws;      /* exponential waiting-time draws (logarithms) */
+    uint64_t round_kernels;  /* round-kernel launches */
+    double round_kernel_ms;  /* HIP-event time of all round launches (cfg.event_timing), else 0 */
 } nh_stats;
 
 /* One simulate request of a batch.  Device pointers; species_out has n slots. */
@@ -169,6 +176,66 @@ int nh_simulate_device(const nh_scenario *scenario, uint64_t seed, const uint64_
  * (n u64) and the richness.  Blocking; uses the default stream. */
 int nh_simulate(const nh_scenario *scenario, uint64_t seed, const uint64_t *h_sample_ids, uint64_t n,
                 uint64_t *h_species_out, uint64_t *h_richness_out, nh_stats *stats);
+
+/* ------------------------------------------------------------------------
+ * Continuous batching (a served request stream).  A server owns a resident
+ * pool of lineage slots in HBM and runs the same round kernels as
+ * nh_batch_run over whichever jobs are admitted: a job submitted while others
+ * are running is admitted at the next round boundary as soon as a contiguous
+ * range of lineage slots (its HBM footprint) and a job slot are free, its
+ * lineages join the shared queue and hash table, and it completes on its own
+ * when its last lineage retires.  Results are bitwise those of nh_simulate.
+ * One thread drives a server; the caller keeps each job's buffers and
+ * scenario alive until its completion is polled.
+ * ------------------------------------------------------------------------ */
+typedef struct nh_server nh_server;
+
+typedef struct {
+    uint64_t lineage_capacity; /* resident lineage slots (the HBM budget / nh_server_bytes per lineage) */
+    uint32_t max_jobs;         /* job slots in flight */
+    uint32_t lookahead;        /* pending jobs past the head that may be admitted first when the head
+                                  does not fit (backfill); 0 = strict FIFO */
+    nh_config cfg;             /* round-kernel tuning; cfg.rounds_per_graph rounds per launch */
+} nh_server_config;
+
+typedef struct {
+    uint64_t tag;       /* the caller's tag from nh_server_submit */
+    int status;         /* NH_OK, or NH_EINVAL if a sample id was not below N */
+    uint32_t rounds;    /* rounds the job took part in */
+    uint64_t richness;
+    uint64_t events;
+    uint64_t lineages;
+    uint64_t speciated;
+    uint64_t merged;
+} nh_completion;
+
+/* Device bytes of a server's resident pool. */
+uint64_t nh_server_bytes(uint64_t lineage_capacity, uint32_t max_jobs);
+
+/* Allocates the pool on the current device and captures the round graph.
+ * stream may be NULL (the server then creates its own non-blocking stream).
+ * Errors: NH_EINVAL for zero capacity or jobs; NH_ENOMEM; NH_EDEVICE. */
+int nh_server_create(const nh_server_config *config, void *stream, nh_server **out);
+
+/* Queues a job (device buffers as in nh_batch_run).  Never blocks.
+ * Errors: NH_EINVAL if the job can never fit (n > lineage_capacity) or has
+ * NULL buffers with n > 0. */
+int nh_server_submit(nh_server *server, const nh_job *job, uint64_t tag);
+
+/* Non-blocking step: collects finished jobs, admits queued jobs that fit,
+ * and keeps round launches in flight while any job is active.  Reports the
+ * jobs on the device and those still queued (either pointer may be NULL). */
+int nh_server_progress(nh_server *server, uint32_t *active, uint32_t *pending);
+
+/* Moves up to max finished jobs into out (oldest first); *n_out receives the count. */
+int nh_server_poll(nh_server *server, nh_completion *out, uint32_t max, uint32_t *n_out);
+
+/* Calls nh_server_progress until nothing is queued, active or resolving.
+ * NH_ETIMEOUT after timeout_s seconds. */
+int nh_server_drain(nh_server *server, double timeout_s);
+
+/* Waits for the server's stream and frees the pool. */
+void nh_server_destroy(nh_server *server);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *nh_last_error(void);

@@ -42,13 +42,14 @@ class nh_params(C.Structure):
 class nh_config(C.Structure):
     _fields_ = [("horizon0", C.c_double), ("horizon_growth", C.c_double), ("horizon_step_max", C.c_double),
                 ("block_size", C.c_uint32), ("blocks_per_cu", C.c_uint32), ("rounds_per_graph", C.c_uint32),
-                ("table_in_lds", C.c_uint32), ("timeout_s", C.c_double)]
+                ("event_timing", C.c_uint32), ("coop_max", C.c_uint32), ("timeout_s", C.c_double)]
 
 
 class nh_stats(C.Structure):
     _fields_ = [("events", C.c_uint64), ("lineages", C.c_uint64), ("speciated", C.c_uint64),
                 ("merged", C.c_uint64), ("rounds", C.c_uint64), ("richness", C.c_uint64),
-                ("device_ms", C.c_double)]
+                ("device_ms", C.c_double), ("philox_calls", C.c_uint64), ("exp_draws", C.c_uint64),
+                ("round_kernels", C.c_uint64), ("round_kernel_ms", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -57,6 +58,19 @@ class nh_stats(C.Structure):
 class nh_job(C.Structure):
     _fields_ = [("scenario", C.c_void_p), ("seed", C.c_uint64), ("d_sample_ids", C.c_void_p), ("n", C.c_uint64),
                 ("d_species_out", C.c_void_p), ("d_richness_out", C.c_void_p)]
+
+
+class nh_server_config(C.Structure):
+    _fields_ = [("lineage_capacity", C.c_uint64), ("max_jobs", C.c_uint32), ("lookahead", C.c_uint32),
+                ("cfg", nh_config)]
+
+
+class nh_completion(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("status", C.c_int), ("rounds", C.c_uint32), ("richness", C.c_uint64),
+                ("events", C.c_uint64), ("lineages", C.c_uint64), ("speciated", C.c_uint64), ("merged", C.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib.nh_scenario_create.argtypes = [C.POINTER(nh_habitat), C.POINTER(nh_dispersal), C.c_double,
@@ -81,6 +95,20 @@ _lib.nh_simulate_device.restype = C.c_int
 _lib.nh_simulate.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64), C.c_uint64, C.POINTER(C.c_uint64),
                              C.POINTER(C.c_uint64), C.POINTER(nh_stats)]
 _lib.nh_simulate.restype = C.c_int
+_lib.nh_server_bytes.argtypes = [C.c_uint64, C.c_uint32]
+_lib.nh_server_bytes.restype = C.c_uint64
+_lib.nh_server_create.argtypes = [C.POINTER(nh_server_config), C.c_void_p, C.POINTER(C.c_void_p)]
+_lib.nh_server_create.restype = C.c_int
+_lib.nh_server_submit.argtypes = [C.c_void_p, C.POINTER(nh_job), C.c_uint64]
+_lib.nh_server_submit.restype = C.c_int
+_lib.nh_server_progress.argtypes = [C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+_lib.nh_server_progress.restype = C.c_int
+_lib.nh_server_poll.argtypes = [C.c_void_p, C.POINTER(nh_completion), C.c_uint32, C.POINTER(C.c_uint32)]
+_lib.nh_server_poll.restype = C.c_int
+_lib.nh_server_drain.argtypes = [C.c_void_p, C.c_double]
+_lib.nh_server_drain.restype = C.c_int
+_lib.nh_server_destroy.argtypes = [C.c_void_p]
+_lib.nh_server_destroy.restype = None
 _lib.nh_last_error.argtypes = []
 _lib.nh_last_error.restype = C.c_char_p
 _lib.nh_version.argtypes = []
@@ -98,10 +126,18 @@ nh_simulate_device = _lib.nh_simulate_device
 nh_simulate = _lib.nh_simulate
 nh_last_error = _lib.nh_last_error
 nh_version = _lib.nh_version
+nh_server_bytes = _lib.nh_server_bytes
+nh_server_create = _lib.nh_server_create
+nh_server_submit = _lib.nh_server_submit
+nh_server_progress = _lib.nh_server_progress
+nh_server_poll = _lib.nh_server_poll
+nh_server_drain = _lib.nh_server_drain
+nh_server_destroy = _lib.nh_server_destroy
 
 EXPORTED = ["nh_scenario_create", "nh_scenario_destroy", "nh_scenario_individuals", "nh_scenario_table_bytes",
             "nh_workspace_bytes", "nh_scenario_footprint_bytes", "nh_batch_run", "nh_simulate_device",
-            "nh_simulate", "nh_last_error", "nh_version"]
+            "nh_simulate", "nh_last_error", "nh_version", "nh_server_bytes", "nh_server_create",
+            "nh_server_submit", "nh_server_progress", "nh_server_poll", "nh_server_drain", "nh_server_destroy"]
 
 
 class NecsimError(RuntimeError):
@@ -190,6 +226,77 @@ def workspace_bytes(n_total: int, n_jobs: int) -> int:
     return int(_lib.nh_workspace_bytes(n_total, n_jobs))
 
 
+def _job(scn, seed, samples, out, rich) -> nh_job:
+    j = nh_job()
+    j.scenario = scn.handle
+    j.seed = int(seed) & (2**64 - 1)
+    j.d_sample_ids = samples.data_ptr() if samples.numel() else None
+    j.n = samples.numel()
+    j.d_species_out = out.data_ptr() if out.numel() else None
+    j.d_richness_out = rich.data_ptr() if rich is not None else None
+    return j
+
+
+def server_bytes(lineage_capacity: int, max_jobs: int) -> int:
+    return int(_lib.nh_server_bytes(lineage_capacity, max_jobs))
+
+
+class Server:
+    """Continuous-batching engine (nh_server_*): a resident lineage pool in HBM that admits jobs
+    while others run.  Keeps each job's tensors and scenario alive until its completion is polled."""
+
+    def __init__(self, lineage_capacity: int, max_jobs: int = 1024, lookahead: int = 16,
+                 config: nh_config | None = None, stream=None):
+        cfg = nh_server_config()
+        cfg.lineage_capacity = lineage_capacity
+        cfg.max_jobs = max_jobs
+        cfg.lookahead = lookahead
+        if config is not None:
+            cfg.cfg = config
+        h = C.c_void_p()
+        st = C.c_void_p(stream.cuda_stream) if stream is not None else None
+        _check(_lib.nh_server_create(C.byref(cfg), st, C.byref(h)), "nh_server_create")
+        self._h = h
+        self._held = {}
+        self._buf = (nh_completion * 512)()
+
+    def submit(self, tag: int, scenario: Scenario, seed: int, samples, out, rich=None, keep=None):
+        j = _job(scenario, seed, samples, out, rich)
+        _check(_lib.nh_server_submit(self._h, C.byref(j), tag), "nh_server_submit")
+        self._held[tag] = (scenario, samples, out, rich, keep)
+
+    def progress(self) -> tuple[int, int]:
+        a, p = C.c_uint32(), C.c_uint32()
+        _check(_lib.nh_server_progress(self._h, C.byref(a), C.byref(p)), "nh_server_progress")
+        return a.value, p.value
+
+    def poll(self) -> list:
+        out = []
+        while True:
+            n = C.c_uint32()
+            _check(_lib.nh_server_poll(self._h, self._buf, len(self._buf), C.byref(n)), "nh_server_poll")
+            for k in range(n.value):
+                d = self._buf[k].as_dict()
+                d["held"] = self._held.pop(d["tag"], None)
+                out.append(d)
+            if n.value < len(self._buf):
+                return out
+
+    def drain(self, timeout_s: float = 600.0):
+        _check(_lib.nh_server_drain(self._h, timeout_s), "nh_server_drain")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.nh_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def batch_run(jobs, workspace, config: nh_config | None = None, stream=None):
     """nh_batch_run over device buffers.
 
@@ -201,12 +308,7 @@ def batch_run(jobs, workspace, config: nh_config | None = None, stream=None):
 
     arr = (nh_job * len(jobs))()
     for k, (scn, seed, samples, out, rich) in enumerate(jobs):
-        arr[k].scenario = scn.handle
-        arr[k].seed = int(seed) & (2**64 - 1)
-        arr[k].d_sample_ids = samples.data_ptr() if samples.numel() else None
-        arr[k].n = samples.numel()
-        arr[k].d_species_out = out.data_ptr() if out.numel() else None
-        arr[k].d_richness_out = rich.data_ptr() if rich is not None else None
+        arr[k] = _job(scn, seed, samples, out, rich)
     st = (nh_stats * len(jobs))()
     s = stream if stream is not None else torch.cuda.current_stream()
     _check(_lib.nh_batch_run(arr, len(jobs), workspace.data_ptr(), workspace.numel(),

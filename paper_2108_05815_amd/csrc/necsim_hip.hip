@@ -66,9 +66,12 @@ int fail(int code, const char *fmt, ...) {
     } while (0)
 
 constexpr uint32_t kErrBadSample = 1u;
+constexpr uint32_t kJobSentinelSpecies = 1u; // JobState.flags: a species id equal to the set's empty marker
+constexpr uint32_t kJobBadSample = 2u;       // JobState.flags: a sample id was not below N
 constexpr uint32_t kErrRunaway = 2u;
 constexpr uint32_t kErrHashFull = 4u;
 constexpr uint32_t kMaxHorizons = 1024;
+constexpr uint32_t kLdsTableMax = 4096; // shared-table entries staged in LDS (64 KiB)
 
 // ---------------------------------------------------------------------------
 // Device data
@@ -95,10 +98,10 @@ struct JobDev {
 
 // Per-job counters, written by the kernels.
 struct JobState {
-    uint32_t remaining;   // lineages not yet retired or merged
-    uint32_t flags;       // bit 0: a species id equal to the set's empty marker was seen
+    uint32_t remaining;   // lineages not yet retired (speciated, merged or rejected)
+    uint32_t flags;       // kJobSentinelSpecies | kJobBadSample
     uint32_t done_round;
-    uint32_t pad;
+    uint32_t start_round; // round before the job's first round
     unsigned long long rich_count;
     unsigned long long events;
     unsigned long long speciated;
@@ -113,12 +116,18 @@ struct Ctl {
     uint32_t blocks_done;
     uint32_t error;
     uint32_t n_jobs;
-    uint32_t pad[6];
+    uint32_t ring_head;  // completions pushed (job slots whose lineages are all retired)
+    uint32_t ring_pub;   // completions already copied to the host-mapped ring
+    unsigned long long philox_calls; // Philox blocks evaluated (all domains)
+    unsigned long long exp_draws;    // exponential waiting-time draws (logarithms)
 };
 
+// Lineage state.  loc/t are double-buffered by round parity: round r reads
+// [r & 1] and writes survivors to [(r + 1) & 1], so the state a cull insert
+// compares against never changes during the kernel that compares it.
 struct Lin {
-    uint32_t *loc;
-    double *t;
+    uint32_t *loc[2];
+    double *t[2];
     uint32_t *parent;
     unsigned long long *species;
     uint32_t *job;
@@ -137,6 +146,11 @@ struct JobView {
     const uint32_t *row_ptr;
     const uint32_t *cap;
     uint32_t W, H, cmax, R, mode, n_shared, cap_const;
+};
+
+// Op counters of one lane (summed per wave at the end of a kernel).
+struct Counters {
+    uint32_t philox = 0, draws = 0;
 };
 
 __device__ __forceinline__ JobView load_view(const JobDev *__restrict__ J) {
@@ -178,6 +192,9 @@ __device__ __forceinline__ void philox10(uint32_t &c0, uint32_t &c1, uint32_t &c
         k1 += 0xBB67AE85u;
     }
 }
+
+// Dynamic LDS: the shared dispersal table of a single-job round kernel.
+extern __shared__ uint4 nh_lds_table[];
 
 // floor(r * n / 2^64) for n < 2^32, from two 32x32->64 products.
 __device__ __forceinline__ uint32_t mulhi_index(uint64_t r, uint32_t n) {
@@ -232,7 +249,8 @@ __device__ __forceinline__ double log_u53o(uint64_t r) {
 // the first sum strictly beyond t_last is the answer.  Returns a negative
 // value (and flags the run) only if the search runs away, which needs a
 // broken scenario.
-__device__ __forceinline__ double next_event_time(const JobView &v, uint32_t loc, double t_last, uint32_t *err) {
+__device__ __forceinline__ double next_event_time(const JobView &v, uint32_t loc, double t_last, uint32_t *err,
+                                                  Counters &cnt) {
     uint64_t k = (uint64_t)floor(t_last * v.inv_dt);
     double e = (double)k * v.dt;
     double end = (double)(k + 1) * v.dt;
@@ -243,12 +261,14 @@ __device__ __forceinline__ double next_event_time(const JobView &v, uint32_t loc
         if ((j & 1u) == 0u) {
             uint32_t c0 = loc, c1 = (uint32_t)k, c2 = (uint32_t)(k >> 32), c3 = j >> 1; // domain 0
             philox10(c0, c1, c2, c3, v.key0, v.key1);
+            ++cnt.philox;
             r = ((uint64_t)c1 << 32) | c0;
             second = ((uint64_t)c3 << 32) | c2;
         } else {
             r = second;
         }
         const double x = (-log_u53o(r)) * v.inv_lambda;
+        ++cnt.draws;
         e = e + x;
         if (e >= end) {
             k += 1;
@@ -285,13 +305,15 @@ __device__ __forceinline__ Pos pos_from_loc(const JobView &v, uint32_t loc) {
 // species id from the species domain; otherwise the alias column from r1, the
 // alias coin from r2, the torus offset of the chosen entry, and the deme index
 // from r3.  Returns true on speciation.
-__device__ __forceinline__ bool commit_event(const JobView &v, Pos &p, double t, uint64_t &species) {
+template <bool kLds = false>
+__device__ __forceinline__ bool commit_event(const JobView &v, Pos &p, double t, uint64_t &species, Counters &cnt) {
     const uint64_t tb = (uint64_t)__double_as_longlong(t);
     const uint32_t tlo = (uint32_t)tb, thi = (uint32_t)(tb >> 32);
     uint32_t a0 = p.loc, a1 = tlo, a2 = thi, a3 = (1u << 30);
     philox10(a0, a1, a2, a3, v.key0, v.key1);
     const uint64_t r0 = ((uint64_t)a1 << 32) | a0;
     const uint64_t r1 = ((uint64_t)a3 << 32) | a2;
+    cnt.philox += 2;
     if ((r0 >> 11) < v.nu_thresh) {
         uint32_t s0 = p.loc, s1 = tlo, s2 = thi, s3 = (2u << 30);
         philox10(s0, s1, s2, s3, v.key0, v.key1);
@@ -312,7 +334,7 @@ __device__ __forceinline__ bool commit_event(const JobView &v, Pos &p, double t,
         n = v.row_ptr[cell + 1] - first;
     }
     const uint32_t col = mulhi_index(r1, n);
-    const uint4 ent = v.table[first + col];
+    const uint4 ent = kLds ? nh_lds_table[first + col] : v.table[first + col];
     const uint64_t thresh = ((uint64_t)ent.y << 32) | ent.x;
     const uint32_t off = ((r2 >> 11) < thresh) ? (ent.z & 0xFFFFu) : (ent.z >> 16);
     int tx = (int)p.x + (int)(off & 0xFFu) - (int)v.R;
@@ -340,24 +362,26 @@ __device__ __forceinline__ uint64_t mix_key(uint32_t loc, uint64_t tb, uint32_t 
     return h;
 }
 
-// Cull table insert for round r: returns g if this lineage becomes the
-// representative of its (job, loc, t_next) state, else the representative's
-// id.  Slots hold (round << 32 | lineage); a slot from an older round is
-// empty.  The owner publishes its state before its CAS (release); readers
-// acquire before comparing the owner's state.
-__device__ __forceinline__ uint32_t cull_insert(const Lin &lin, uint32_t r, uint32_t g, uint32_t loc, uint64_t tb,
-                                                uint32_t job, uint32_t *err) {
+// Cull insert at the start of round r, for a lineage taken from the round's
+// queue with state (job, loc, t_next) = state_in[g].  Returns g if it becomes
+// the representative of that state, else the representative's id.  Slots hold
+// (r << 32 | lineage); a slot of an older round is empty.  Every state compared
+// here was written by an earlier kernel and is read-only in this one, so the
+// only synchronisation needed is the slot's own atomic.
+__device__ __forceinline__ uint32_t cull_insert(const Lin &lin, const uint32_t *__restrict__ loc_in,
+                                                const double *__restrict__ t_in, uint32_t r, uint32_t g,
+                                                uint32_t loc, uint64_t tb, uint32_t job, uint32_t *err) {
     uint32_t idx = (uint32_t)mix_key(loc, tb, job) & lin.hmask;
     const unsigned long long mine = ((unsigned long long)r << 32) | g;
     for (uint32_t probe = 0; probe <= lin.hmask; ++probe) {
-        unsigned long long cur = __hip_atomic_load(&lin.hash[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long cur = __hip_atomic_load(&lin.hash[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         while ((uint32_t)(cur >> 32) != r) {
-            if (__hip_atomic_compare_exchange_strong(&lin.hash[idx], &cur, mine, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+            if (__hip_atomic_compare_exchange_strong(&lin.hash[idx], &cur, mine, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT))
                 return g;
         }
         const uint32_t owner = (uint32_t)cur;
-        if (lin.loc[owner] == loc && (uint64_t)__double_as_longlong(lin.t[owner]) == tb && lin.job[owner] == job)
+        if (loc_in[owner] == loc && (uint64_t)__double_as_longlong(t_in[owner]) == tb && lin.job[owner] == job)
             return owner;
         idx = (idx + 1u) & lin.hmask;
     }
@@ -367,6 +391,42 @@ __device__ __forceinline__ uint32_t cull_insert(const Lin &lin, uint32_t r, uint
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// Horizon of a job's lr-th round: the host table, extended linearly by the
+// table's last step beyond its end.
+__device__ __forceinline__ double horizon_of(const double *__restrict__ htab, uint32_t lr) {
+    if (lr < kMaxHorizons) return htab[lr];
+    const double step = htab[kMaxHorizons - 1] - htab[kMaxHorizons - 2];
+    return htab[kMaxHorizons - 1] + (double)(lr - (kMaxHorizons - 1)) * step;
+}
+
+// Wave sum of a u64 over all 64 lanes.
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// Op counters: per-wave sums go to LDS, one global atomic per workgroup.
+// Every thread of the block must call it.
+__device__ __forceinline__ void flush_counters_block(Ctl *ctl, const Counters &c) {
+    __shared__ unsigned long long acc[2];
+    if (threadIdx.x == 0) {
+        acc[0] = 0;
+        acc[1] = 0;
+    }
+    __syncthreads();
+    const unsigned long long ph = wave_sum(c.philox), dr = wave_sum(c.draws);
+    if (lane_id() == 0 && (ph | dr)) {
+        atomicAdd(&acc[0], ph);
+        atomicAdd(&acc[1], dr);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && (acc[0] | acc[1])) {
+        atomicAdd(&ctl->philox_calls, acc[0]);
+        atomicAdd(&ctl->exp_draws, acc[1]);
+    }
+}
+
 __device__ __forceinline__ uint32_t wave_reserve(uint64_t mask, uint32_t *counter) {
     // One atomic per wave for the lanes set in mask; each lane gets base + rank.
     const uint32_t lane = lane_id();
@@ -375,6 +435,142 @@ __device__ __forceinline__ uint32_t wave_reserve(uint64_t mask, uint32_t *counte
     if ((int)lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
     base = __shfl(base, leader, 64);
     return base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t x, int src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, src, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ double shfl_f64(double x, int src) {
+    return __longlong_as_double((long long)shfl_u64((uint64_t)__double_as_longlong(x), src));
+}
+
+// ---------------------------------------------------------------------------
+// Cooperative forms for lineages that are few: a group of 8 lanes works on
+// one lineage and evaluates the independent Philox blocks of one event side
+// by side.  Results are bit-identical to the one-lane functions above.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kGroup = 8;
+
+// Next event time with lane gl of the group on interval k + gl (+ 8 per
+// extra batch).  Every lane takes the first draw of its interval on one common
+// code path.  Lane 0 of the first batch holds the interval containing t_last
+// and, when that first sum has neither left the interval nor passed t_last,
+// keeps walking exactly as next_event_time() does; every later interval
+// starts beyond t_last, so its first draw alone decides it (an event iff it
+// lands before the interval's end).  The answer is the hit of the lowest
+// interval.  Counters record the draws the one-lane search would have made.
+__device__ __forceinline__ double next_event_time_group(const JobView &v, uint32_t loc, double t_last, uint32_t gl,
+                                                        uint32_t grp_base, uint32_t *err, Counters &cnt) {
+    const uint64_t k0 = (uint64_t)floor(t_last * v.inv_dt);
+    for (uint32_t batch = 0; batch < (1u << 20); ++batch) {
+        const uint64_t k = k0 + (uint64_t)batch * kGroup + gl;
+        double e = (double)k * v.dt;
+        const double end = (double)(k + 1) * v.dt;
+        uint32_t c0 = loc, c1 = (uint32_t)k, c2 = (uint32_t)(k >> 32), c3 = 0; // domain 0, call 0
+        philox10(c0, c1, c2, c3, v.key0, v.key1);
+        uint64_t second = ((uint64_t)c3 << 32) | c2;
+        e = e + (-log_u53o(((uint64_t)c1 << 32) | c0)) * v.inv_lambda;
+        uint32_t my_philox = 1, my_draws = 1;
+        bool hit = e < end;
+        if (batch == 0 && gl == 0 && hit && !(e > t_last)) {
+            hit = false;
+            for (uint32_t j = 1; j < (1u << 24); ++j) {
+                uint64_t r;
+                if ((j & 1u) == 0u) {
+                    uint32_t d0 = loc, d1 = (uint32_t)k, d2 = (uint32_t)(k >> 32), d3 = j >> 1;
+                    philox10(d0, d1, d2, d3, v.key0, v.key1);
+                    ++my_philox;
+                    r = ((uint64_t)d1 << 32) | d0;
+                    second = ((uint64_t)d3 << 32) | d2;
+                } else {
+                    r = second;
+                }
+                ++my_draws;
+                e = e + (-log_u53o(r)) * v.inv_lambda;
+                if (e >= end) break;
+                if (e > t_last) {
+                    hit = true;
+                    break;
+                }
+            }
+        }
+        const uint32_t hits = (uint32_t)((__ballot(hit) >> grp_base) & 0xFFu);
+        const uint32_t upto = hits ? (uint32_t)(__ffs(hits) - 1) : kGroup - 1; // last interval consumed
+        if (gl == 0) { // lane 0's own draws plus one block and one draw per later interval consumed
+            if (batch == 0) {
+                cnt.philox += my_philox + upto;
+                cnt.draws += my_draws + upto;
+            } else {
+                cnt.philox += upto + 1;
+                cnt.draws += upto + 1;
+            }
+        }
+        if (hits) return shfl_f64(e, (int)(grp_base + __ffs(hits) - 1));
+    }
+    atomicOr(err, kErrRunaway);
+    return -1.0;
+}
+
+// Swap a 32-bit value with the neighbouring lane (lane ^ 1): one DPP move.
+__device__ __forceinline__ uint32_t swap_neighbour(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1 /* quad_perm [1,0,3,2] */, 0xF, 0xF, false);
+}
+
+// One event for a group: even lanes evaluate event block 0 and odd lanes
+// event block 1 side by side and swap words with their neighbour, so every
+// lane holds r0..r3; the species block is evaluated (by every lane) only when
+// the lineage speciates.  Every lane then applies the same speciation test and
+// dispersal, so the group stays in agreement without further exchange.
+template <bool kLds = false>
+__device__ __forceinline__ bool commit_event_group(const JobView &v, Pos &p, double t, uint64_t &species,
+                                                   uint32_t gl, uint32_t grp_base, Counters &cnt) {
+    const uint64_t tb = (uint64_t)__double_as_longlong(t);
+    const uint32_t tlo = (uint32_t)tb, thi = (uint32_t)(tb >> 32);
+    const uint32_t call = gl & 1u;
+    uint32_t a0 = p.loc, a1 = tlo, a2 = thi, a3 = (1u << 30) | call;
+    philox10(a0, a1, a2, a3, v.key0, v.key1);
+    const uint32_t b0 = swap_neighbour(a0), b1 = swap_neighbour(a1), b2 = swap_neighbour(a2),
+                   b3 = swap_neighbour(a3);
+    const uint64_t wa = ((uint64_t)a1 << 32) | a0, wb = ((uint64_t)a3 << 32) | a2; // my block
+    const uint64_t xa = ((uint64_t)b1 << 32) | b0, xb = ((uint64_t)b3 << 32) | b2; // neighbour's block
+    const uint64_t r0 = call ? xa : wa, r1 = call ? xb : wb;
+    const uint64_t r2 = call ? wa : xa, r3 = call ? wb : xb;
+    if (gl == 0) cnt.philox += 2;
+    if ((r0 >> 11) < v.nu_thresh) {
+        uint32_t s0 = p.loc, s1 = tlo, s2 = thi, s3 = (2u << 30);
+        philox10(s0, s1, s2, s3, v.key0, v.key1);
+        species = ((uint64_t)s1 << 32) | s0;
+        return true;
+    }
+    uint32_t first, n;
+    if (v.mode == NH_DISPERSAL_SHARED) {
+        first = 0;
+        n = v.n_shared;
+    } else {
+        const uint32_t cell = p.y * v.W + p.x;
+        first = v.row_ptr[cell];
+        n = v.row_ptr[cell + 1] - first;
+    }
+    const uint32_t col = mulhi_index(r1, n);
+    const uint4 ent = kLds ? nh_lds_table[first + col] : v.table[first + col];
+    const uint64_t thresh = ((uint64_t)ent.y << 32) | ent.x;
+    const uint32_t off = ((r2 >> 11) < thresh) ? (ent.z & 0xFFFFu) : (ent.z >> 16);
+    int tx = (int)p.x + (int)(off & 0xFFu) - (int)v.R;
+    int ty = (int)p.y + (int)(off >> 8) - (int)v.R;
+    if (tx < 0) tx += (int)v.W;
+    else if (tx >= (int)v.W) tx -= (int)v.W;
+    if (ty < 0) ty += (int)v.H;
+    else if (ty >= (int)v.H) ty -= (int)v.H;
+    const uint32_t target = (uint32_t)ty * v.W + (uint32_t)tx;
+    const uint32_t capt = v.cap_const ? v.cap_const : v.cap[target];
+    p.x = (uint32_t)tx;
+    p.y = (uint32_t)ty;
+    p.i = mulhi_index(r3, capt);
+    p.loc = target * v.cmax + p.i;
+    return false;
 }
 
 // ---------------------------------------------------------------------------
@@ -396,11 +592,16 @@ __global__ void k_setup(Ctl *ctl, JobState *js, const JobDev *jobs, uint32_t n_j
         ctl->blocks_done = 0;
         ctl->error = 0;
         ctl->n_jobs = n_jobs;
+        ctl->philox_calls = 0;
+        ctl->exp_draws = 0;
+        ctl->ring_head = 0;
+        ctl->ring_pub = 0;
     }
     for (uint32_t j = t; j < n_jobs; j += gridDim.x * blockDim.x) {
         js[j].remaining = jobs[j].n;
         js[j].flags = 0;
         js[j].done_round = 0;
+        js[j].start_round = jobs[j].start_round;
         js[j].rich_count = 0;
         js[j].events = 0;
         js[j].speciated = 0;
@@ -419,15 +620,58 @@ __device__ __forceinline__ uint32_t job_of(const JobDev *jobs, uint32_t n_jobs, 
     return lo;
 }
 
+struct RoundArgs {
+    Ctl *ctl;
+    const JobDev *jobs;
+    JobState *js;
+    uint32_t *ring;    // completion ring (device), ring_cap slots
+    Lin lin;
+    const double *htab;
+    uint32_t coop_max; // queues shorter than this run groups of 8 lanes per lineage
+    uint32_t ring_cap;
+};
+
+// Retires lineages (speciated, merged, or rejected at init) from their jobs'
+// live counts, one atomic per wave when the retiring lanes share a job.  The
+// lane that brings a job to zero records the round and pushes the job onto
+// the completion ring.  All active lanes call it.
+__device__ __forceinline__ void job_retired(Ctl *ctl, JobState *js, uint32_t *ring, uint32_t ring_cap, uint32_t r,
+                                            uint32_t jb, uint32_t count) {
+    const uint32_t old = atomicSub(&js[jb].remaining, count);
+    if (old == count) {
+        js[jb].done_round = r;
+        const uint32_t at = atomicAdd(&ctl->ring_head, 1u);
+        ring[at % ring_cap] = jb;
+    }
+}
+
+__device__ __forceinline__ void wave_retire(Ctl *ctl, JobState *js, uint32_t *ring, uint32_t ring_cap, uint32_t r,
+                                            bool retiring, uint32_t jb) {
+    const uint64_t m = __ballot(retiring);
+    if (!m) return;
+    const int first = __ffsll((unsigned long long)m) - 1;
+    const uint32_t jb0 = __shfl(jb, first, 64);
+    if (__ballot(retiring && jb != jb0) == 0) {
+        if (lane_id() == (uint32_t)first) job_retired(ctl, js, ring, ring_cap, r, jb0, (uint32_t)__popcll(m));
+    } else if (retiring) {
+        job_retired(ctl, js, ring, ring_cap, r, jb, 1u);
+    }
+}
+
 // Lineage init: dense sample id -> (cell, deme index) -> loc; first event time
-// from t = 0; append to the current round's queue.  An id >= N flags the run
-// and the lineage is left out of the queue.
-__global__ void k_init(Ctl *ctl, const JobDev *__restrict__ jobs, uint32_t n_jobs, Lin lin, uint32_t g_begin,
-                       uint32_t g_end) {
+// from t = 0; append to the current round's queue.  Lineages [g_begin, g_end)
+// belong to job `fixed_job`, or (fixed_job < 0) to the job found by binary
+// search over jobs sorted by lineage base.  An id >= N flags the job (and the
+// run) and the lineage is retired at once instead of queued.
+__global__ void k_init(Ctl *ctl, const JobDev *__restrict__ jobs, uint32_t n_jobs, int fixed_job, JobState *js,
+                       uint32_t *ring, uint32_t ring_cap, Lin lin, uint32_t g_begin, uint32_t g_end) {
     const uint32_t g = g_begin + blockIdx.x * blockDim.x + threadIdx.x;
-    bool push = false;
+    const uint32_t r = ctl->round;
+    bool push = false, bad = false;
+    uint32_t jb = 0;
+    Counters cnt;
     if (g < g_end) {
-        const uint32_t jb = job_of(jobs, n_jobs, g);
+        jb = fixed_job >= 0 ? (uint32_t)fixed_job : job_of(jobs, n_jobs, g);
         const JobDev *J = &jobs[jb];
         const JobView v = load_view(J);
         const uint64_t id = J->samples[g - J->lin_base];
@@ -435,6 +679,8 @@ __global__ void k_init(Ctl *ctl, const JobDev *__restrict__ jobs, uint32_t n_job
         double t = 0.0;
         if (id >= J->n_individuals) {
             atomicOr(&ctl->error, kErrBadSample);
+            atomicOr(&js[jb].flags, kJobBadSample);
+            bad = true;
         } else {
             const uint32_t cells = v.W * v.H;
             uint32_t lo = 0, hi = cells; // last cell with prefix <= id
@@ -444,11 +690,12 @@ __global__ void k_init(Ctl *ctl, const JobDev *__restrict__ jobs, uint32_t n_job
                 else hi = mid;
             }
             loc = lo * v.cmax + (uint32_t)(id - J->prefix[lo]);
-            t = next_event_time(v, loc, 0.0, &ctl->error);
+            t = next_event_time(v, loc, 0.0, &ctl->error, cnt);
             push = t >= 0.0;
+            bad = !push;
         }
-        lin.loc[g] = loc;
-        lin.t[g] = t;
+        lin.loc[r & 1][g] = loc;
+        lin.t[r & 1][g] = t;
         lin.parent[g] = g;
         lin.species[g] = 0;
         lin.job[g] = jb;
@@ -456,69 +703,162 @@ __global__ void k_init(Ctl *ctl, const JobDev *__restrict__ jobs, uint32_t n_job
     }
     const uint64_t mask = __ballot(push);
     if (mask) {
-        const uint32_t r = ctl->round;
         const uint32_t slot = wave_reserve(mask, &ctl->count[r % 3]);
         if (push) lin.act[r & 1][slot] = g;
     }
+    wave_retire(ctl, js, ring, ring_cap, r, bad, jb);
+    flush_counters_block(ctl, cnt);
 }
 
-// One horizon round over every queued lineage of every job.
-template <bool kSingleJob>
-__global__ __launch_bounds__(256) void k_round(Ctl *__restrict__ ctl, const JobDev *__restrict__ jobs,
-                                               JobState *__restrict__ js, Lin lin, const double *__restrict__ htab,
-                                               unsigned long long *status_host) {
-    const uint32_t r = ctl->round;
-    const uint32_t qin = r % 3, qout = (r + 1) % 3;
-    const uint32_t n_in = ctl->count[qin];
+// Admission of one job into a running engine: its counters, its species set
+// and its first round (the job's horizons count from the round it joins).
+__global__ void k_job_setup(Ctl *ctl, JobDev *jobs, JobState *js, uint32_t slot) {
+    JobDev *J = &jobs[slot];
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid == 0) {
+        J->start_round = ctl->round - 1;
+        js[slot].start_round = ctl->round - 1;
+        js[slot].remaining = J->n;
+        js[slot].flags = 0;
+        js[slot].done_round = 0;
+        js[slot].rich_count = 0;
+        js[slot].events = 0;
+        js[slot].speciated = 0;
+        js[slot].merged = 0;
+    }
+    for (uint64_t i = tid; i <= (uint64_t)J->rich_mask; i += (uint64_t)gridDim.x * blockDim.x) J->rich_set[i] = ~0ull;
+}
+
+// Round kernels.  Round r takes the queue of round r, drops lineages whose
+// (job, loc, t_next) another lineage already holds (cull), advances the rest
+// event by event until the next event lies beyond the job's horizon, retires
+// speciated lineages and queues the others for round r + 1.  Two lane
+// layouts: one lane per lineage (many lineages), or a group of 8 lanes per
+// lineage when the queue is short enough that the chip would otherwise idle.
+// Per-wave access to the round's queues with few atomics.  Input: the wave
+// reserves chunks of the queue with one atomic and hands items to its idle
+// lanes from the chunk.  Output: survivors are staged in a per-wave LDS
+// buffer and appended to the next queue one buffer-full at a time.
+constexpr uint32_t kWavesPerBlock = 4; // block size 256 at most
+constexpr uint32_t kOutBuf = 256;      // staged survivor ids per wave
+
+struct WaveQueues {
+    uint32_t chunk_pos = 0, chunk_end = 0; // wave-uniform: unread part of the reserved chunk
+    bool open = true;                      // wave-uniform: the round's queue may still hold items
+    uint32_t staged = 0;                   // wave-uniform: ids in this wave's output buffer
+};
+
+// Hands out at most one queue position per lane in `want`; returns the
+// position (or ~0u) for each wanting lane.  All active lanes call it.  A
+// reservation takes max(#wanting, chunk) items: chunk is the caller's fair
+// share, so a short queue is spread over many waves instead of one.
+__device__ __forceinline__ uint32_t wave_take(WaveQueues &q, uint64_t want, uint32_t *cursor, uint32_t n_in,
+                                              uint32_t chunk) {
+    const uint32_t lane = lane_id();
+    chunk = max(chunk, (uint32_t)__popcll(want));
+    if (q.chunk_pos >= q.chunk_end && q.open) {
+        const int leader = __ffsll((unsigned long long)__ballot(1)) - 1;
+        uint32_t base = 0;
+        if ((int)lane == leader) base = atomicAdd(cursor, chunk);
+        base = __shfl(base, leader, 64);
+        if (base >= n_in) {
+            q.open = false;
+            q.chunk_pos = q.chunk_end = 0;
+        } else {
+            q.chunk_pos = base;
+            q.chunk_end = min(base + chunk, n_in);
+            if (q.chunk_end == n_in) q.open = false;
+        }
+    }
+    const uint32_t avail = q.chunk_end - q.chunk_pos;
+    const uint32_t rank = (uint32_t)__popcll(want & ((1ull << lane) - 1ull));
+    const uint32_t pos = ((want >> lane) & 1ull) && rank < avail ? q.chunk_pos + rank : 0xFFFFFFFFu;
+    q.chunk_pos += min((uint32_t)__popcll(want), avail);
+    return pos;
+}
+
+__device__ __forceinline__ void wave_flush(WaveQueues &q, uint32_t *buf, uint32_t *count_out, uint32_t *act_out) {
+    if (q.staged == 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t lane = lane_id();
+    const int leader = __ffsll((unsigned long long)__ballot(1)) - 1;
+    uint32_t base = 0;
+    if ((int)lane == leader) base = atomicAdd(count_out, q.staged);
+    base = __shfl(base, leader, 64);
+    for (uint32_t i = lane; i < q.staged; i += 64) act_out[base + i] = buf[i];
+    __builtin_amdgcn_wave_barrier();
+    q.staged = 0;
+}
+
+// Stages the ids of lanes with `push` set; flushes when the buffer is nearly full.
+__device__ __forceinline__ void wave_push(WaveQueues &q, bool push, uint32_t id, uint32_t *buf, uint32_t *count_out,
+                                          uint32_t *act_out) {
+    const uint64_t pm = __ballot(push);
+    if (!pm) return;
+    const uint32_t lane = lane_id();
+    if (push) buf[q.staged + (uint32_t)__popcll(pm & ((1ull << lane) - 1ull))] = id;
+    q.staged += (uint32_t)__popcll(pm);
+    if (q.staged > kOutBuf - 64) wave_flush(q, buf, count_out, act_out);
+}
+
+template <bool kSingleJob, bool kLds>
+__device__ __forceinline__ void round_one_lane(const RoundArgs &A, uint32_t r, uint32_t n_in, Counters &cnt,
+                                               uint32_t *obuf, uint32_t chunk) {
+    Ctl *ctl = A.ctl;
+    const Lin &lin = A.lin;
     const uint32_t *__restrict__ act_in = lin.act[r & 1];
     uint32_t *__restrict__ act_out = lin.act[(r + 1) & 1];
+    const uint32_t *__restrict__ loc_in = lin.loc[r & 1];
+    const double *__restrict__ t_in = lin.t[r & 1];
+    uint32_t *__restrict__ loc_out = lin.loc[(r + 1) & 1];
+    double *__restrict__ t_out = lin.t[(r + 1) & 1];
     uint32_t *err = &ctl->error;
+    const uint32_t qin = r % 3, qout = (r + 1) % 3;
 
     JobView v;
     double w_single = 0.0;
     if (kSingleJob) {
-        v = load_view(&jobs[0]);
-        const uint32_t lr = r - jobs[0].start_round;
-        w_single = htab[lr < kMaxHorizons ? lr : kMaxHorizons - 1];
+        v = load_view(&A.jobs[0]);
+        w_single = horizon_of(A.htab, r - A.jobs[0].start_round);
     }
-
-    bool has = false, queue_open = n_in > 0;
+    WaveQueues q;
+    bool has = false;
     uint32_t g = 0, jb = 0, ev = 0;
     Pos p = {0, 0, 0, 0};
-    double t = 0.0, horizon = 0.0;
+    double t = 0.0, horizon = w_single;
 
     while (true) {
-        // Refill idle lanes from the queue: one atomic per wave.
-        if (queue_open) {
-            const uint64_t need = __ballot(!has);
-            if (need) {
-                const uint32_t lane = lane_id();
-                const int leader = __ffsll((unsigned long long)need) - 1;
-                uint32_t base = 0;
-                if ((int)lane == leader) base = atomicAdd(&ctl->cursor[qin], (uint32_t)__popcll(need));
-                base = __shfl(base, leader, 64);
-                if (base + (uint32_t)__popcll(need) >= n_in) queue_open = false;
-                if (!has) {
-                    const uint32_t idx = base + (uint32_t)__popcll(need & ((1ull << lane) - 1ull));
-                    if (idx < n_in) {
-                        g = act_in[idx];
-                        if (!kSingleJob) {
-                            jb = lin.job[g];
-                            v = load_view(&jobs[jb]);
-                            const uint32_t lr = r - jobs[jb].start_round;
-                            horizon = htab[lr < kMaxHorizons ? lr : kMaxHorizons - 1];
-                        } else {
-                            horizon = w_single;
-                        }
-                        p = pos_from_loc(v, lin.loc[g]);
-                        t = lin.t[g];
-                        ev = 0;
-                        has = true;
+        const uint64_t need = __ballot(!has);
+        bool retire = false;
+        if (need && (q.open || q.chunk_pos < q.chunk_end)) {
+            const uint32_t pos = wave_take(q, need, &ctl->cursor[qin], n_in, chunk);
+            if (pos != 0xFFFFFFFFu) {
+                g = act_in[pos];
+                if (!kSingleJob) jb = lin.job[g];
+                const uint32_t loc = loc_in[g];
+                t = t_in[g];
+                const uint32_t owner =
+                    cull_insert(lin, loc_in, t_in, r, g, loc, (uint64_t)__double_as_longlong(t), jb, err);
+                if (owner != g) {
+                    lin.parent[g] = owner;
+                    retire = true;
+                } else {
+                    if (!kSingleJob) {
+                        v = load_view(&A.jobs[jb]);
+                        horizon = horizon_of(A.htab, r - A.jobs[jb].start_round);
                     }
+                    p = pos_from_loc(v, loc);
+                    ev = 0;
+                    has = true;
                 }
             }
         }
-        if (__ballot(has) == 0) break;
+        if (__ballot(has) == 0) {
+            wave_retire(ctl, A.js, A.ring, A.ring_cap, r, retire, jb);
+            if (!q.open && q.chunk_pos >= q.chunk_end) break;
+            continue;
+        }
 
         bool finish_live = false, finish_dead = false;
         uint64_t sp = 0;
@@ -527,10 +867,10 @@ __global__ __launch_bounds__(256) void k_round(Ctl *__restrict__ ctl, const JobD
                 finish_live = true;
             } else {
                 ++ev;
-                if (commit_event(v, p, t, sp)) {
+                if (commit_event<kLds>(v, p, t, sp, cnt)) {
                     finish_dead = true;
                 } else {
-                    t = next_event_time(v, p.loc, t, err);
+                    t = next_event_time(v, p.loc, t, err, cnt);
                     if (t < 0.0) finish_dead = true; // runaway search (flagged)
                     else if (t > horizon) finish_live = true;
                 }
@@ -541,58 +881,180 @@ __global__ __launch_bounds__(256) void k_round(Ctl *__restrict__ ctl, const JobD
             lin.events[g] += ev;
             has = false;
         }
-        bool push = false;
         if (finish_live) {
-            lin.loc[g] = p.loc;
-            lin.t[g] = t;
+            loc_out[g] = p.loc;
+            t_out[g] = t;
             lin.events[g] += ev;
-            const uint32_t owner =
-                cull_insert(lin, r, g, p.loc, (uint64_t)__double_as_longlong(t), jb, err);
-            if (owner != g) {
-                lin.parent[g] = owner;
+            has = false;
+        }
+        wave_retire(ctl, A.js, A.ring, A.ring_cap, r, retire || finish_dead, jb);
+        wave_push(q, finish_live, g, obuf, &ctl->count[qout], act_out);
+    }
+    wave_flush(q, obuf, &ctl->count[qout], act_out);
+}
+
+template <bool kSingleJob, bool kLds>
+__device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint32_t n_in, Counters &cnt,
+                                            uint32_t *obuf, uint32_t chunk) {
+    Ctl *ctl = A.ctl;
+    const Lin &lin = A.lin;
+    const uint32_t *__restrict__ act_in = lin.act[r & 1];
+    uint32_t *__restrict__ act_out = lin.act[(r + 1) & 1];
+    const uint32_t *__restrict__ loc_in = lin.loc[r & 1];
+    const double *__restrict__ t_in = lin.t[r & 1];
+    uint32_t *__restrict__ loc_out = lin.loc[(r + 1) & 1];
+    double *__restrict__ t_out = lin.t[(r + 1) & 1];
+    uint32_t *err = &ctl->error;
+    const uint32_t qin = r % 3, qout = (r + 1) % 3;
+    const uint32_t lane = lane_id(), gl = lane & (kGroup - 1), grp_base = lane & ~(kGroup - 1);
+    const bool leader = gl == 0;
+
+    JobView v;
+    double w_single = 0.0;
+    if (kSingleJob) {
+        v = load_view(&A.jobs[0]);
+        w_single = horizon_of(A.htab, r - A.jobs[0].start_round);
+    }
+    WaveQueues q;
+    bool has = false;
+    uint32_t g = 0, jb = 0, ev = 0;
+    Pos p = {0, 0, 0, 0};
+    double t = 0.0, horizon = w_single;
+
+    while (true) {
+        const uint64_t need = __ballot(leader && !has);
+        bool retire = false;     // set on the leader lane of a group whose candidate was merged
+        uint32_t retire_jb = 0;
+        if (need && (q.open || q.chunk_pos < q.chunk_end)) {
+            const uint32_t pos = wave_take(q, need, &ctl->cursor[qin], n_in, chunk);
+            uint32_t take = 0xFFFFFFFFu; // lineage id the group leader took, or none
+            if (pos != 0xFFFFFFFFu) {
+                const uint32_t cand = act_in[pos];
+                const uint32_t cjb = kSingleJob ? 0u : lin.job[cand];
+                const uint32_t owner = cull_insert(lin, loc_in, t_in, r, cand, loc_in[cand],
+                                                   (uint64_t)__double_as_longlong(t_in[cand]), cjb, err);
+                if (owner != cand) {
+                    lin.parent[cand] = owner;
+                    retire = true;
+                    retire_jb = cjb;
+                } else {
+                    take = cand;
+                }
+            }
+            take = (uint32_t)__shfl((int)take, (int)grp_base, 64);
+            if (!has && take != 0xFFFFFFFFu) {
+                g = take;
+                if (!kSingleJob) {
+                    jb = lin.job[g];
+                    v = load_view(&A.jobs[jb]);
+                    horizon = horizon_of(A.htab, r - A.jobs[jb].start_round);
+                }
+                p = pos_from_loc(v, loc_in[g]);
+                t = t_in[g];
+                ev = 0;
+                has = true;
+            }
+        }
+        if (__ballot(has) == 0) {
+            wave_retire(ctl, A.js, A.ring, A.ring_cap, r, retire, retire_jb);
+            if (!q.open && q.chunk_pos >= q.chunk_end) break;
+            continue;
+        }
+
+        bool finish_live = false, finish_dead = false;
+        uint64_t sp = 0;
+        if (has) {
+            if (t > horizon) {
+                finish_live = true;
             } else {
-                push = true;
+                ++ev;
+                if (commit_event_group<kLds>(v, p, t, sp, gl, grp_base, cnt)) {
+                    finish_dead = true;
+                } else {
+                    t = next_event_time_group(v, p.loc, t, gl, grp_base, err, cnt);
+                    if (t < 0.0) finish_dead = true;
+                    else if (t > horizon) finish_live = true;
+                }
+            }
+        }
+        if (finish_dead) {
+            if (leader) {
+                lin.species[g] = sp;
+                lin.events[g] += ev;
             }
             has = false;
         }
-        const uint64_t pm = __ballot(push);
-        if (pm) {
-            const uint32_t slot = wave_reserve(pm, &ctl->count[qout]);
-            if (push) act_out[slot] = g;
+        if (finish_live) {
+            if (leader) {
+                loc_out[g] = p.loc;
+                t_out[g] = t;
+                lin.events[g] += ev;
+            }
+            has = false;
         }
+        // a group leader retires either the candidate it merged at pickup or its speciated lineage
+        const bool dead_leader = finish_dead && leader;
+        wave_retire(ctl, A.js, A.ring, A.ring_cap, r, retire || dead_leader, retire ? retire_jb : jb);
+        wave_push(q, finish_live && leader, g, obuf, &ctl->count[qout], act_out);
     }
-
-    // Last workgroup of the round: advance the round and publish the status.
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t done = atomicAdd(&ctl->blocks_done, 1u);
-        if (done == gridDim.x - 1) {
-            __threadfence();
-            const uint32_t n_out = __hip_atomic_load(&ctl->count[qout], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-            ctl->blocks_done = 0;
-            ctl->count[(r + 2) % 3] = 0;
-            ctl->cursor[qout] = 0;
-            ctl->round = r + 1;
-            const unsigned long long word =
-                ((unsigned long long)(r + 1) << 32) | n_out | ((unsigned long long)(ctl->error != 0) << 31);
-            __hip_atomic_store(status_host, word, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
-    }
+    wave_flush(q, obuf, &ctl->count[qout], act_out);
 }
 
-// Wave sum of a u64 over all 64 lanes.
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
+template <bool kSingleJob, bool kLds>
+__global__ __launch_bounds__(256) void k_round(RoundArgs A) {
+    const uint32_t r = A.ctl->round;
+    const uint32_t n_in = A.ctl->count[r % 3];
+    if (n_in == 0) return;
+    const bool group = n_in < A.coop_max;
+    const uint64_t lanes_needed = (uint64_t)n_in * (group ? kGroup : 1u);
+    const uint64_t blocks_needed = (lanes_needed + blockDim.x - 1) / blockDim.x;
+    if (blockIdx.x >= blocks_needed) return; // whole workgroup leaves together
+    if (kLds) { // stage the shared dispersal table (single job, shared mode, small table)
+        const uint32_t n_tab = A.jobs[0].n_shared;
+        const uint4 *__restrict__ src = A.jobs[0].table;
+        for (uint32_t i = threadIdx.x; i < n_tab; i += blockDim.x) nh_lds_table[i] = src[i];
+        __syncthreads();
+    }
+    __shared__ uint32_t out_stage[kWavesPerBlock][kOutBuf];
+    uint32_t *obuf = out_stage[threadIdx.x / 64];
+    // fair share of the queue per participating wave (a quarter of it per reservation), capped
+    const uint64_t waves = min((uint64_t)gridDim.x, blocks_needed) * (blockDim.x / 64);
+    const uint32_t chunk = (uint32_t)min<uint64_t>(group ? 32u : 256u, n_in / (4 * waves));
+    Counters cnt;
+    if (group) round_group<kSingleJob, kLds>(A, r, n_in, cnt, obuf, chunk);
+    else round_one_lane<kSingleJob, kLds>(A, r, n_in, cnt, obuf, chunk);
+    flush_counters_block(A.ctl, cnt);
+}
+
+// Single-thread epilogue of a round: publish the survivor count to the
+// host-mapped status word and new job completions to the host-mapped ring,
+// advance the round, reset the next queues.
+__global__ void k_advance(Ctl *ctl, unsigned long long *status_host, const uint32_t *ring, uint32_t ring_cap,
+                          uint32_t *ring_host) {
+    const uint32_t r = ctl->round;
+    const uint32_t n_out = ctl->count[(r + 1) % 3];
+    ctl->count[(r + 2) % 3] = 0;
+    ctl->cursor[(r + 1) % 3] = 0;
+    ctl->round = r + 1;
+    if (ring_host) {
+        const uint32_t head = ctl->ring_head;
+        for (uint32_t i = ctl->ring_pub; i != head; ++i)
+            __hip_atomic_store(&ring_host[1 + i % ring_cap], ring[i % ring_cap], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+        ctl->ring_pub = head;
+        __hip_atomic_store(&ring_host[0], head, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    // a bad sample id only fails its own job (reported at completion); other flags stop the run
+    const unsigned long long word = ((unsigned long long)(r + 1) << 32) | n_out |
+                                    ((unsigned long long)((ctl->error & ~kErrBadSample) != 0) << 31);
+    __hip_atomic_store(status_host, word, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Output: follow merge pointers to the representative, write species per
 // sample; representatives insert their species into the job's set.  Counters
 // are summed per wave when the whole wave belongs to one job.
-__global__ void k_resolve(const JobDev *__restrict__ jobs, uint32_t n_jobs, JobState *js, Lin lin, uint32_t g_end) {
-    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_resolve(const JobDev *__restrict__ jobs, JobState *js, Lin lin, uint32_t g_begin, uint32_t g_end) {
+    const uint32_t g = g_begin + blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = g < g_end;
     uint32_t jb = 0;
     unsigned long long events = 0;
@@ -608,7 +1070,7 @@ __global__ void k_resolve(const JobDev *__restrict__ jobs, uint32_t n_jobs, JobS
         is_root = x == g;
         if (is_root) {
             if (sp == ~0ull) {
-                atomicOr(&js[jb].flags, 1u);
+                atomicOr(&js[jb].flags, kJobSentinelSpecies);
             } else {
                 uint32_t idx = (uint32_t)sp & J->rich_mask;
                 for (uint32_t probe = 0; probe <= J->rich_mask; ++probe) {
@@ -643,10 +1105,10 @@ __global__ void k_resolve(const JobDev *__restrict__ jobs, uint32_t n_jobs, JobS
     }
 }
 
-__global__ void k_finalize(const JobDev *__restrict__ jobs, uint32_t n_jobs, JobState *js) {
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_jobs) return;
-    const unsigned long long rich = js[j].rich_count + ((js[j].flags & 1u) ? 1ull : 0ull);
+__global__ void k_finalize(const JobDev *__restrict__ jobs, JobState *js, uint32_t j_begin, uint32_t j_end) {
+    const uint32_t j = j_begin + blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= j_end) return;
+    const unsigned long long rich = js[j].rich_count + ((js[j].flags & kJobSentinelSpecies) ? 1ull : 0ull);
     js[j].rich_count = rich;
     if (jobs[j].richness_out) *jobs[j].richness_out = rich;
 }
@@ -778,22 +1240,45 @@ struct nh_scenario {
 
 namespace {
 
+// Library-internal non-blocking stream per device: scenario tables are
+// allocated, uploaded and freed stream-ordered on it, so creating or
+// destroying a scenario never synchronises work on other streams.
+hipStream_t table_stream(int device) {
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0 || device >= 64) return nullptr;
+    if (!streams[device]) {
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(device);
+        if (hipStreamCreateWithFlags(&streams[device], hipStreamNonBlocking) != hipSuccess) streams[device] = nullptr;
+        (void)hipSetDevice(prev);
+    }
+    return streams[device];
+}
+
 void scenario_free(nh_scenario *s) {
     if (!s) return;
+    if (s->device < 0 || !(s->d_table || s->d_row_ptr || s->d_cap || s->d_prefix)) {
+        delete s;
+        return;
+    }
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(s->device);
-    if (s->d_table) (void)hipFree(s->d_table);
-    if (s->d_row_ptr) (void)hipFree(s->d_row_ptr);
-    if (s->d_cap) (void)hipFree(s->d_cap);
-    if (s->d_prefix) (void)hipFree(s->d_prefix);
+    hipStream_t ts = table_stream(s->device);
+    if (s->d_table) (void)hipFreeAsync(s->d_table, ts);
+    if (s->d_row_ptr) (void)hipFreeAsync(s->d_row_ptr, ts);
+    if (s->d_cap) (void)hipFreeAsync(s->d_cap, ts);
+    if (s->d_prefix) (void)hipFreeAsync(s->d_prefix, ts);
     (void)hipSetDevice(prev);
     delete s;
 }
 
 struct Workspace {
-    uint64_t off_ctl, off_jobs, off_js, off_htab, off_loc, off_t, off_parent, off_species, off_job, off_events,
-        off_act0, off_act1, off_hash, off_rich, total;
+    uint64_t off_ctl, off_jobs, off_js, off_ring, off_htab, off_loc0, off_loc1, off_t0, off_t1, off_parent, off_species,
+        off_job, off_events, off_act0, off_act1, off_hash, off_rich, total;
     uint64_t hcap;
 };
 
@@ -809,9 +1294,12 @@ Workspace layout(uint64_t n_total, uint32_t n_jobs) {
     w.off_ctl = take(sizeof(Ctl));
     w.off_jobs = take(sizeof(JobDev) * std::max<uint32_t>(n_jobs, 1));
     w.off_js = take(sizeof(JobState) * std::max<uint32_t>(n_jobs, 1));
+    w.off_ring = take(sizeof(uint32_t) * std::max<uint32_t>(n_jobs, 1));
     w.off_htab = take(sizeof(double) * kMaxHorizons);
-    w.off_loc = take(4 * N);
-    w.off_t = take(8 * N);
+    w.off_loc0 = take(4 * N);
+    w.off_loc1 = take(4 * N);
+    w.off_t0 = take(8 * N);
+    w.off_t1 = take(8 * N);
     w.off_parent = take(4 * N);
     w.off_species = take(8 * N);
     w.off_job = take(4 * N);
@@ -853,6 +1341,7 @@ void fill_config(const nh_config *in, nh_config &c) {
     if (c.block_size == 0) c.block_size = 256;
     if (c.blocks_per_cu == 0) c.blocks_per_cu = 4;
     if (c.rounds_per_graph == 0) c.rounds_per_graph = 8;
+    /* coop_max 0 = default (lanes of one launch / 8); 1 keeps one lane per lineage for every queue > 1 */
     if (!(c.timeout_s > 0)) c.timeout_s = 600.0;
 }
 
@@ -916,7 +1405,8 @@ NH_API int nh_scenario_create(const nh_habitat *habitat, const nh_dispersal *dis
     if (cells * (uint64_t)cmax >= (1ull << 32)) return fail(NH_EINVAL, "width*height*max capacity must be < 2^32");
 
     nh_scenario *s = new nh_scenario();
-    (void)hipGetDevice(&s->device);
+    if (hipGetDevice(&s->device) != hipSuccess) s->device = -1;
+    hipStream_t ts = nullptr; // the device is touched only after every validation has passed
     s->W = W;
     s->H = H;
     s->R = R;
@@ -943,16 +1433,22 @@ NH_API int nh_scenario_create(const nh_habitat *habitat, const nh_dispersal *dis
         return code;
     };
 
+    auto device_stream = [&]() -> bool {
+        if (!ts) ts = table_stream(s->device);
+        return ts != nullptr;
+    };
     if (s->mode == NH_DISPERSAL_SHARED) {
         const uint32_t n = tb.count(-1);
         if (n == 0) return bail(fail(NH_EINVAL, "all dispersal weights are zero"));
+        if (!device_stream()) return bail(fail(NH_EDEVICE, "no HIP device for the scenario tables"));
         std::vector<uint4> host(n);
         tb.build(-1, host.data());
         s->n_shared = n;
         s->n_entries = n;
-        if (hipMalloc(&s->d_table, sizeof(uint4) * n) != hipSuccess)
+        if (hipMallocAsync((void **)&s->d_table, sizeof(uint4) * n, ts) != hipSuccess)
             return bail(fail(NH_ENOMEM, "device table allocation failed"));
-        if (hipMemcpy(s->d_table, host.data(), sizeof(uint4) * n, hipMemcpyHostToDevice) != hipSuccess)
+        if (hipMemcpyAsync(s->d_table, host.data(), sizeof(uint4) * n, hipMemcpyHostToDevice, ts) != hipSuccess ||
+            hipStreamSynchronize(ts) != hipSuccess)
             return bail(fail(NH_EDEVICE, "table upload failed"));
     } else {
         // Per-deme tables in CSR order, built by host threads in chunks and
@@ -983,11 +1479,13 @@ NH_API int nh_scenario_create(const nh_habitat *habitat, const nh_dispersal *dis
         }
         row[cells] = (uint32_t)total;
         s->n_entries = total;
-        if (hipMalloc(&s->d_table, sizeof(uint4) * std::max<uint64_t>(total, 1)) != hipSuccess)
+        if (!device_stream()) return bail(fail(NH_EDEVICE, "no HIP device for the scenario tables"));
+        if (hipMallocAsync((void **)&s->d_table, sizeof(uint4) * std::max<uint64_t>(total, 1), ts) != hipSuccess)
             return bail(fail(NH_ENOMEM, "device table allocation (%llu entries) failed", (unsigned long long)total));
-        if (hipMalloc(&s->d_row_ptr, sizeof(uint32_t) * (cells + 1)) != hipSuccess)
+        if (hipMallocAsync((void **)&s->d_row_ptr, sizeof(uint32_t) * (cells + 1), ts) != hipSuccess)
             return bail(fail(NH_ENOMEM, "row pointer allocation failed"));
-        if (hipMemcpy(s->d_row_ptr, row.data(), sizeof(uint32_t) * (cells + 1), hipMemcpyHostToDevice) != hipSuccess)
+        if (hipMemcpyAsync(s->d_row_ptr, row.data(), sizeof(uint32_t) * (cells + 1), hipMemcpyHostToDevice, ts) !=
+            hipSuccess)
             return bail(fail(NH_EDEVICE, "row pointer upload failed"));
         const uint64_t chunk_entries = 1ull << 24; // 256 MB staging
         std::vector<uint4> stage((size_t)std::min<uint64_t>(chunk_entries + side * side, total + 1));
@@ -1007,16 +1505,20 @@ NH_API int nh_scenario_create(const nh_habitat *habitat, const nh_dispersal *dis
             }
             for (auto &th : pool) th.join();
             const uint64_t n = (uint64_t)row[c1] - base;
-            if (n && hipMemcpy(s->d_table + base, stage.data(), sizeof(uint4) * n, hipMemcpyHostToDevice) != hipSuccess)
+            if (n && (hipMemcpyAsync(s->d_table + base, stage.data(), sizeof(uint4) * n, hipMemcpyHostToDevice, ts) !=
+                          hipSuccess ||
+                      hipStreamSynchronize(ts) != hipSuccess))
                 return bail(fail(NH_EDEVICE, "table upload failed"));
             c0 = c1;
         }
     }
-    if (hipMalloc(&s->d_cap, sizeof(uint32_t) * cells) != hipSuccess ||
-        hipMalloc(&s->d_prefix, sizeof(uint64_t) * (cells + 1)) != hipSuccess)
+    if (hipMallocAsync((void **)&s->d_cap, sizeof(uint32_t) * cells, ts) != hipSuccess ||
+        hipMallocAsync((void **)&s->d_prefix, sizeof(uint64_t) * (cells + 1), ts) != hipSuccess)
         return bail(fail(NH_ENOMEM, "capacity allocation failed"));
-    if (hipMemcpy(s->d_cap, cap, sizeof(uint32_t) * cells, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(s->d_prefix, prefix.data(), sizeof(uint64_t) * (cells + 1), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpyAsync(s->d_cap, cap, sizeof(uint32_t) * cells, hipMemcpyHostToDevice, ts) != hipSuccess ||
+        hipMemcpyAsync(s->d_prefix, prefix.data(), sizeof(uint64_t) * (cells + 1), hipMemcpyHostToDevice, ts) !=
+            hipSuccess ||
+        hipStreamSynchronize(ts) != hipSuccess)
         return bail(fail(NH_EDEVICE, "capacity upload failed"));
     s->table_bytes = sizeof(uint4) * s->n_entries + (s->d_row_ptr ? 4 * (cells + 1) : 0) + 4 * cells + 8 * (cells + 1);
     *out = s;
@@ -1065,9 +1567,13 @@ NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, 
     JobDev *d_jobs = (JobDev *)(ws + L.off_jobs);
     JobState *d_js = (JobState *)(ws + L.off_js);
     double *d_htab = (double *)(ws + L.off_htab);
+    uint32_t *d_ring = (uint32_t *)(ws + L.off_ring);
+    const uint32_t ring_cap = std::max<uint32_t>(n_jobs, 1);
     Lin lin;
-    lin.loc = (uint32_t *)(ws + L.off_loc);
-    lin.t = (double *)(ws + L.off_t);
+    lin.loc[0] = (uint32_t *)(ws + L.off_loc0);
+    lin.loc[1] = (uint32_t *)(ws + L.off_loc1);
+    lin.t[0] = (double *)(ws + L.off_t0);
+    lin.t[1] = (double *)(ws + L.off_t1);
     lin.parent = (uint32_t *)(ws + L.off_parent);
     lin.species = (unsigned long long *)(ws + L.off_species);
     lin.job = (uint32_t *)(ws + L.off_job);
@@ -1147,7 +1653,8 @@ NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, 
     if (rich_off) k_fill_u64<<<1024, 256, 0, stream>>>(rich, rich_off, ~0ull);
     if (n_total) {
         const uint32_t blocks = (uint32_t)((n_total + 255) / 256);
-        k_init<<<blocks, 256, 0, stream>>>(ctl, d_jobs, n_jobs, lin, 0, (uint32_t)n_total);
+        k_init<<<blocks, 256, 0, stream>>>(ctl, d_jobs, n_jobs, -1, d_js, d_ring, ring_cap, lin, 0,
+                                           (uint32_t)n_total);
     }
     HIP_TRY(hipGetLastError());
     // The status word: round 0 and "not finished" until the first round kernel reports.
@@ -1156,44 +1663,100 @@ NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, 
     // Round kernels: replayed from a captured graph of cfg.rounds_per_graph launches.
     const uint32_t grid = (uint32_t)std::max(1, n_cu) * cfg.blocks_per_cu;
     const bool single = n_jobs == 1;
+    RoundArgs ra;
+    std::memset(&ra, 0, sizeof ra);
+    ra.ctl = ctl;
+    ra.jobs = d_jobs;
+    ra.lin = lin;
+    ra.htab = d_htab;
+    ra.js = d_js;
+    ra.ring = d_ring;
+    ra.ring_cap = ring_cap;
+    ra.coop_max = cfg.coop_max ? cfg.coop_max : (uint32_t)(((uint64_t)grid * cfg.block_size) / kGroup) + 1;
+    const nh_scenario *s0 = jobs[0].scenario;
+    const bool lds_table = single && s0->mode == NH_DISPERSAL_SHARED && s0->n_shared <= kLdsTableMax;
+    const size_t lds_bytes = lds_table ? sizeof(uint4) * s0->n_shared : 0;
     auto launch_round = [&](hipStream_t s) {
-        if (single)
-            k_round<true><<<grid, cfg.block_size, 0, s>>>(ctl, d_jobs, d_js, lin, d_htab, st.dev);
+        if (lds_table)
+            k_round<true, true><<<grid, cfg.block_size, lds_bytes, s>>>(ra);
+        else if (single)
+            k_round<true, false><<<grid, cfg.block_size, 0, s>>>(ra);
         else
-            k_round<false><<<grid, cfg.block_size, 0, s>>>(ctl, d_jobs, d_js, lin, d_htab, st.dev);
+            k_round<false, false><<<grid, cfg.block_size, 0, s>>>(ra);
+        k_advance<<<1, 1, 0, s>>>(ctl, st.dev, d_ring, ring_cap, nullptr);
     };
-    hipGraph_t graph = nullptr;
+    // Instantiated graphs are cached per thread: a graph bakes in the kernel
+    // arguments, which depend only on the workspace, the lane layout and the
+    // status word, so repeated runs on one workspace reuse it.
+    struct GraphEntry {
+        RoundArgs ra;
+        uint32_t grid, block, rounds, variant;
+        size_t lds;
+        unsigned long long *status;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    thread_local std::vector<GraphEntry> graph_cache;
     hipGraphExec_t exec = nullptr;
-    struct GraphGuard {
-        hipGraph_t &g;
-        hipGraphExec_t &e;
-        ~GraphGuard() {
-            if (e) (void)hipGraphExecDestroy(e);
-            if (g) (void)hipGraphDestroy(g);
-        }
-    } gg{graph, exec};
     bool use_graph = cfg.rounds_per_graph > 1;
+    const uint32_t variant = lds_table ? 2u : (single ? 1u : 0u);
     if (use_graph && n_total) {
-        hipStream_t cap_stream;
-        HIP_TRY(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
-        hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            for (uint32_t k = 0; k < cfg.rounds_per_graph; ++k) launch_round(cap_stream);
-            e = hipStreamEndCapture(cap_stream, &graph);
+        for (auto &ge : graph_cache) {
+            if (ge.grid == grid && ge.block == cfg.block_size && ge.rounds == cfg.rounds_per_graph &&
+                ge.variant == variant && ge.lds == lds_bytes && ge.status == st.dev &&
+                std::memcmp(&ge.ra, &ra, sizeof ra) == 0) {
+                exec = ge.exec;
+                break;
+            }
         }
-        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipStreamDestroy(cap_stream);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            use_graph = false;
+        if (!exec) {
+            hipGraph_t graph = nullptr;
+            hipStream_t cap_stream;
+            HIP_TRY(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+            hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                for (uint32_t k = 0; k < cfg.rounds_per_graph; ++k) launch_round(cap_stream);
+                e = hipStreamEndCapture(cap_stream, &graph);
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipStreamDestroy(cap_stream);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                if (graph) (void)hipGraphDestroy(graph);
+                exec = nullptr;
+                use_graph = false;
+            } else {
+                if (graph_cache.size() >= 8) {
+                    (void)hipGraphExecDestroy(graph_cache.front().exec);
+                    (void)hipGraphDestroy(graph_cache.front().graph);
+                    graph_cache.erase(graph_cache.begin());
+                }
+                graph_cache.push_back(GraphEntry{ra, grid, cfg.block_size, cfg.rounds_per_graph, variant, lds_bytes,
+                                                 st.dev, graph, exec});
+            }
         }
     }
     const uint32_t per_launch = use_graph ? cfg.rounds_per_graph : 1;
     uint64_t rounds_enqueued = 0;
+    // Optional HIP-event bracketing of every round launch (graph or kernel).
+    thread_local std::vector<hipEvent_t> ev_pool;
+    uint32_t ev_used = 0;
     auto enqueue = [&]() -> int {
+        if (cfg.event_timing) {
+            while (ev_pool.size() < 2ull * (ev_used + 1)) {
+                hipEvent_t e;
+                HIP_TRY(hipEventCreate(&e));
+                ev_pool.push_back(e);
+            }
+            HIP_TRY(hipEventRecord(ev_pool[2 * ev_used], stream));
+        }
         if (use_graph) HIP_TRY(hipGraphLaunch(exec, stream));
         else launch_round(stream);
         HIP_TRY(hipGetLastError());
+        if (cfg.event_timing) {
+            HIP_TRY(hipEventRecord(ev_pool[2 * ev_used + 1], stream));
+            ++ev_used;
+        }
         rounds_enqueued += per_launch;
         return NH_OK;
     };
@@ -1229,9 +1792,9 @@ NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, 
             }
         }
         const uint32_t blocks = (uint32_t)((n_total + 255) / 256);
-        k_resolve<<<blocks, 256, 0, stream>>>(d_jobs, n_jobs, d_js, lin, (uint32_t)n_total);
+        k_resolve<<<blocks, 256, 0, stream>>>(d_jobs, d_js, lin, 0, (uint32_t)n_total);
     }
-    k_finalize<<<(n_jobs + 255) / 256, 256, 0, stream>>>(d_jobs, n_jobs, d_js);
+    k_finalize<<<(n_jobs + 255) / 256, 256, 0, stream>>>(d_jobs, d_js, 0, n_jobs);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(ev1, stream));
     std::vector<JobState> hs(n_jobs);
@@ -1243,6 +1806,12 @@ NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, 
     if (hctl.error) return fail(NH_EDEVICE, "kernel reported error flags 0x%x", hctl.error);
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+    double round_ms = 0.0;
+    for (uint32_t k = 0; k < ev_used; ++k) {
+        float x = 0.f;
+        HIP_TRY(hipEventElapsedTime(&x, ev_pool[2 * k], ev_pool[2 * k + 1]));
+        round_ms += x;
+    }
     if (stats) {
         for (uint32_t j = 0; j < n_jobs; ++j) {
             stats[j].events = hs[j].events;
@@ -1252,6 +1821,10 @@ NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, 
             stats[j].rounds = final_round;
             stats[j].richness = hs[j].rich_count;
             stats[j].device_ms = ms;
+            stats[j].philox_calls = hctl.philox_calls;
+            stats[j].exp_draws = hctl.exp_draws;
+            stats[j].round_kernels = rounds_enqueued;
+            stats[j].round_kernel_ms = round_ms;
         }
     }
     return NH_OK;
@@ -1304,3 +1877,430 @@ NH_API int nh_simulate(const nh_scenario *scenario, uint64_t seed, const uint64_
     if (h_richness_out) *h_richness_out = rich;
     return NH_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Continuous batching: nh_server
+// ---------------------------------------------------------------------------
+namespace {
+
+// First-fit allocator of [start, start + len) ranges with coalescing frees.
+struct RangeAlloc {
+    std::vector<std::pair<uint64_t, uint64_t>> free; // sorted by start: (start, len)
+    void reset(uint64_t total) {
+        free.clear();
+        if (total) free.emplace_back(0, total);
+    }
+    bool alloc(uint64_t n, uint64_t &at) {
+        for (size_t k = 0; k < free.size(); ++k) {
+            if (free[k].second >= n) {
+                at = free[k].first;
+                free[k].first += n;
+                free[k].second -= n;
+                if (free[k].second == 0) free.erase(free.begin() + (long)k);
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t at, uint64_t n) {
+        if (n == 0) return;
+        size_t k = 0;
+        while (k < free.size() && free[k].first < at) ++k;
+        free.insert(free.begin() + (long)k, {at, n});
+        if (k + 1 < free.size() && free[k].first + free[k].second == free[k + 1].first) {
+            free[k].second += free[k + 1].second;
+            free.erase(free.begin() + (long)k + 1);
+        }
+        if (k > 0 && free[k - 1].first + free[k - 1].second == free[k].first) {
+            free[k - 1].second += free[k].second;
+            free.erase(free.begin() + (long)k);
+        }
+    }
+};
+
+enum SlotState { kSlotFree = 0, kSlotActive = 1, kSlotResolving = 2 };
+
+struct ServerSlot {
+    int state = kSlotFree;
+    uint64_t tag = 0;
+    nh_job job{};
+    uint64_t lin_base = 0, n = 0, rich_base = 0, rich_slots = 0;
+    hipEvent_t ev = nullptr;
+};
+
+} // namespace
+
+struct nh_server {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    nh_config cfg{};
+    uint64_t cap_lin = 0;
+    uint32_t max_jobs = 0, lookahead = 0;
+    void *ws = nullptr;
+    Workspace L{};
+    Ctl *ctl = nullptr;
+    JobDev *d_jobs = nullptr;
+    JobState *d_js = nullptr;
+    uint32_t *d_ring = nullptr;
+    double *d_htab = nullptr;
+    Lin lin{};
+    unsigned long long *rich = nullptr;
+    uint64_t rich_total = 0;
+    // host-mapped / pinned
+    unsigned long long *status_h = nullptr, *status_d = nullptr;
+    uint32_t *ring_h = nullptr, *ring_hd = nullptr;
+    JobState *js_h = nullptr;
+    JobDev *jobdev_h = nullptr;
+    RangeAlloc lin_alloc, rich_alloc;
+    std::vector<ServerSlot> slots;
+    std::vector<uint32_t> free_slots;
+    std::vector<std::pair<nh_job, uint64_t>> pending;
+    std::vector<nh_completion> done;
+    uint32_t ring_read = 0;
+    uint32_t active = 0, resolving = 0;
+    uint64_t rounds_enqueued = 0;
+    uint32_t grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void server_free(nh_server *s) {
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (auto &sl : s->slots)
+        if (sl.ev) (void)hipEventDestroy(sl.ev);
+    if (s->exec) (void)hipGraphExecDestroy(s->exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    if (s->ws) (void)hipFree(s->ws);
+    if (s->status_h) (void)hipHostFree(s->status_h);
+    if (s->ring_h) (void)hipHostFree(s->ring_h);
+    if (s->js_h) (void)hipHostFree(s->js_h);
+    if (s->jobdev_h) (void)hipHostFree(s->jobdev_h);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+void job_descriptor(JobDev &d, const nh_job &job, unsigned long long *rich_set, uint64_t rich_slots,
+                    uint64_t lin_base) {
+    const nh_scenario *sc = job.scenario;
+    std::memset(&d, 0, sizeof d);
+    d.seed = job.seed;
+    d.nu_thresh = sc->nu_thresh;
+    d.inv_lambda = 1.0 / sc->lambda;
+    d.dt = sc->dt;
+    d.inv_dt = 1.0 / sc->dt;
+    d.table = sc->d_table;
+    d.row_ptr = sc->d_row_ptr;
+    d.cap = sc->d_cap;
+    d.prefix = sc->d_prefix;
+    d.samples = job.d_sample_ids;
+    d.species_out = (unsigned long long *)job.d_species_out;
+    d.richness_out = (unsigned long long *)job.d_richness_out;
+    d.rich_set = rich_set;
+    d.rich_mask = (uint32_t)(rich_slots - 1);
+    d.n_individuals = sc->N;
+    d.W = sc->W;
+    d.H = sc->H;
+    d.cmax = sc->cmax;
+    d.R = sc->R;
+    d.mode = sc->mode;
+    d.n_shared = sc->n_shared;
+    d.cap_const = sc->cap_const;
+    d.lin_base = (uint32_t)lin_base;
+    d.n = (uint32_t)job.n;
+    d.start_round = 0;
+}
+
+int server_launch_round(nh_server *s) {
+    if (s->exec) HIP_TRY(hipGraphLaunch(s->exec, s->stream));
+    else return fail(NH_EDEVICE, "server round graph missing");
+    HIP_TRY(hipGetLastError());
+    s->rounds_enqueued += s->cfg.rounds_per_graph;
+    return NH_OK;
+}
+
+int server_admit(nh_server *s, const nh_job &job, uint64_t tag, bool &admitted) {
+    admitted = false;
+    if (s->free_slots.empty()) return NH_OK;
+    const uint64_t rich_slots = pow2_at_least(2 * job.n, 64);
+    uint64_t lin_at = 0, rich_at = 0;
+    if (job.n && !s->lin_alloc.alloc(job.n, lin_at)) return NH_OK;
+    if (!s->rich_alloc.alloc(rich_slots, rich_at)) {
+        if (job.n) s->lin_alloc.release(lin_at, job.n);
+        return NH_OK;
+    }
+    const uint32_t slot = s->free_slots.back();
+    s->free_slots.pop_back();
+    ServerSlot &sl = s->slots[slot];
+    sl.state = kSlotActive;
+    sl.tag = tag;
+    sl.job = job;
+    sl.lin_base = lin_at;
+    sl.n = job.n;
+    sl.rich_base = rich_at;
+    sl.rich_slots = rich_slots;
+    JobDev &d = s->jobdev_h[slot];
+    job_descriptor(d, job, s->rich + rich_at, rich_slots, lin_at);
+    HIP_TRY(hipMemcpyAsync(&s->d_jobs[slot], &d, sizeof(JobDev), hipMemcpyHostToDevice, s->stream));
+    const uint32_t fill_blocks = (uint32_t)std::min<uint64_t>(1024, (rich_slots + 255) / 256);
+    k_job_setup<<<fill_blocks, 256, 0, s->stream>>>(s->ctl, s->d_jobs, s->d_js, slot);
+    if (job.n) {
+        const uint32_t blocks = (uint32_t)((job.n + 255) / 256);
+        k_init<<<blocks, 256, 0, s->stream>>>(s->ctl, s->d_jobs, s->max_jobs, (int)slot, s->d_js, s->d_ring,
+                                               s->max_jobs, s->lin, (uint32_t)lin_at, (uint32_t)(lin_at + job.n));
+    } else {
+        // nothing to simulate: resolve (richness 0) right away
+        k_finalize<<<1, 1, 0, s->stream>>>(s->d_jobs, s->d_js, slot, slot + 1);
+        HIP_TRY(hipMemcpyAsync(&s->js_h[slot], &s->d_js[slot], sizeof(JobState), hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipEventRecord(sl.ev, s->stream));
+        sl.state = kSlotResolving;
+        ++s->resolving;
+        admitted = true;
+        return NH_OK;
+    }
+    HIP_TRY(hipGetLastError());
+    ++s->active;
+    admitted = true;
+    return NH_OK;
+}
+
+} // namespace
+
+NH_API uint64_t nh_server_bytes(uint64_t lineage_capacity, uint32_t max_jobs) {
+    return layout(lineage_capacity, max_jobs).total;
+}
+
+NH_API int nh_server_create(const nh_server_config *config, void *stream, nh_server **out) {
+    if (!out) return fail(NH_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!config || config->lineage_capacity == 0 || config->max_jobs == 0)
+        return fail(NH_EINVAL, "server needs a positive lineage capacity and job count");
+    if (config->lineage_capacity >= (1ull << 31)) return fail(NH_EINVAL, "lineage capacity must be < 2^31");
+    nh_server *s = new nh_server();
+    fill_config(&config->cfg, s->cfg);
+    if (s->cfg.block_size % 64 != 0 || s->cfg.block_size > 256) {
+        delete s;
+        return fail(NH_EINVAL, "block_size must be a multiple of 64 up to 256");
+    }
+    s->cap_lin = config->lineage_capacity;
+    s->max_jobs = config->max_jobs;
+    s->lookahead = config->lookahead;
+    auto bail = [&](int code) {
+        server_free(s);
+        return code;
+    };
+    if (hipGetDevice(&s->device) != hipSuccess) return bail(fail(NH_EDEVICE, "no HIP device"));
+    if (stream) {
+        s->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(NH_EDEVICE, "stream creation failed"));
+        s->own_stream = true;
+    }
+    s->L = layout(s->cap_lin, s->max_jobs);
+    if (hipMalloc(&s->ws, s->L.total) != hipSuccess)
+        return bail(fail(NH_ENOMEM, "server pool of %llu bytes", (unsigned long long)s->L.total));
+    char *ws = (char *)s->ws;
+    s->ctl = (Ctl *)(ws + s->L.off_ctl);
+    s->d_jobs = (JobDev *)(ws + s->L.off_jobs);
+    s->d_js = (JobState *)(ws + s->L.off_js);
+    s->d_ring = (uint32_t *)(ws + s->L.off_ring);
+    s->d_htab = (double *)(ws + s->L.off_htab);
+    s->lin.loc[0] = (uint32_t *)(ws + s->L.off_loc0);
+    s->lin.loc[1] = (uint32_t *)(ws + s->L.off_loc1);
+    s->lin.t[0] = (double *)(ws + s->L.off_t0);
+    s->lin.t[1] = (double *)(ws + s->L.off_t1);
+    s->lin.parent = (uint32_t *)(ws + s->L.off_parent);
+    s->lin.species = (unsigned long long *)(ws + s->L.off_species);
+    s->lin.job = (uint32_t *)(ws + s->L.off_job);
+    s->lin.events = (uint32_t *)(ws + s->L.off_events);
+    s->lin.act[0] = (uint32_t *)(ws + s->L.off_act0);
+    s->lin.act[1] = (uint32_t *)(ws + s->L.off_act1);
+    s->lin.hash = (unsigned long long *)(ws + s->L.off_hash);
+    s->lin.hmask = (uint32_t)(s->L.hcap - 1);
+    s->rich = (unsigned long long *)(ws + s->L.off_rich);
+    s->rich_total = 4 * s->cap_lin + 64ull * s->max_jobs;
+    void *h = nullptr;
+    if (hipHostMalloc(&h, 256, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+        return bail(fail(NH_ENOMEM, "pinned status allocation failed"));
+    s->status_h = (unsigned long long *)h;
+    if (hipHostGetDevicePointer((void **)&s->status_d, h, 0) != hipSuccess)
+        return bail(fail(NH_EDEVICE, "status mapping failed"));
+    if (hipHostMalloc(&h, sizeof(uint32_t) * (1 + s->max_jobs), hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
+        return bail(fail(NH_ENOMEM, "pinned ring allocation failed"));
+    s->ring_h = (uint32_t *)h;
+    std::memset(s->ring_h, 0, sizeof(uint32_t) * (1 + s->max_jobs));
+    if (hipHostGetDevicePointer((void **)&s->ring_hd, h, 0) != hipSuccess)
+        return bail(fail(NH_EDEVICE, "ring mapping failed"));
+    if (hipHostMalloc(&h, sizeof(JobState) * s->max_jobs, hipHostMallocDefault) != hipSuccess)
+        return bail(fail(NH_ENOMEM, "pinned job-state allocation failed"));
+    s->js_h = (JobState *)h;
+    if (hipHostMalloc(&h, sizeof(JobDev) * s->max_jobs, hipHostMallocDefault) != hipSuccess)
+        return bail(fail(NH_ENOMEM, "pinned job staging allocation failed"));
+    s->jobdev_h = (JobDev *)h;
+    s->slots.resize(s->max_jobs);
+    for (uint32_t k = 0; k < s->max_jobs; ++k) {
+        if (hipEventCreateWithFlags(&s->slots[k].ev, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(NH_EDEVICE, "event creation failed"));
+        s->free_slots.push_back(s->max_jobs - 1 - k);
+    }
+    s->lin_alloc.reset(s->cap_lin);
+    s->rich_alloc.reset(s->rich_total);
+    __atomic_store_n(s->status_h, (unsigned long long)1, __ATOMIC_SEQ_CST);
+
+    const std::vector<double> htab = horizon_table(s->cfg);
+    if (hipMemcpyAsync(s->d_htab, htab.data(), sizeof(double) * kMaxHorizons, hipMemcpyHostToDevice, s->stream) !=
+        hipSuccess)
+        return bail(fail(NH_EDEVICE, "horizon upload failed"));
+    k_setup<<<1, 256, 0, s->stream>>>(s->ctl, s->d_js, s->d_jobs, 0, 1);
+    k_fill_u64<<<1024, 256, 0, s->stream>>>(s->lin.hash, s->L.hcap, 0ull);
+    if (hipGetLastError() != hipSuccess) return bail(fail(NH_EDEVICE, "server setup launch failed"));
+
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess)
+        return bail(fail(NH_EDEVICE, "device query failed"));
+    s->grid = (uint32_t)std::max(1, n_cu) * s->cfg.blocks_per_cu;
+    RoundArgs ra;
+    std::memset(&ra, 0, sizeof ra);
+    ra.ctl = s->ctl;
+    ra.jobs = s->d_jobs;
+    ra.js = s->d_js;
+    ra.ring = s->d_ring;
+    ra.ring_cap = s->max_jobs;
+    ra.lin = s->lin;
+    ra.htab = s->d_htab;
+    ra.coop_max = s->cfg.coop_max ? s->cfg.coop_max : (uint32_t)(((uint64_t)s->grid * s->cfg.block_size) / kGroup) + 1;
+    hipStream_t cap_stream;
+    if (hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(NH_EDEVICE, "capture stream creation failed"));
+    hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (uint32_t k = 0; k < s->cfg.rounds_per_graph; ++k) {
+            k_round<false, false><<<s->grid, s->cfg.block_size, 0, cap_stream>>>(ra);
+            k_advance<<<1, 1, 0, cap_stream>>>(s->ctl, s->status_d, s->d_ring, s->max_jobs, s->ring_hd);
+        }
+        e = hipStreamEndCapture(cap_stream, &s->graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cap_stream);
+    if (e != hipSuccess) return bail(fail(NH_EDEVICE, "round graph capture failed: %s", hipGetErrorString(e)));
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(fail(NH_EDEVICE, "server setup failed"));
+    *out = s;
+    return NH_OK;
+}
+
+NH_API int nh_server_submit(nh_server *s, const nh_job *job, uint64_t tag) {
+    if (!s || !job || !job->scenario) return fail(NH_EINVAL, "NULL server, job or scenario");
+    if (job->n > 0 && (!job->d_sample_ids || !job->d_species_out))
+        return fail(NH_EINVAL, "NULL sample or output buffer");
+    if (job->n > s->cap_lin)
+        return fail(NH_EINVAL, "job of %llu lineages exceeds the server capacity %llu", (unsigned long long)job->n,
+                    (unsigned long long)s->cap_lin);
+    if (pow2_at_least(2 * job->n, 64) > s->rich_total) return fail(NH_EINVAL, "job too large for the species pool");
+    s->pending.emplace_back(*job, tag);
+    return NH_OK;
+}
+
+NH_API int nh_server_progress(nh_server *s, uint32_t *active_out, uint32_t *pending_out) {
+    if (!s) return fail(NH_EINVAL, "NULL server");
+    // (a) completions published by the round epilogue
+    const uint32_t head = __atomic_load_n(&s->ring_h[0], __ATOMIC_ACQUIRE);
+    while (s->ring_read != head) {
+        const uint32_t slot = __atomic_load_n(&s->ring_h[1 + s->ring_read % s->max_jobs], __ATOMIC_ACQUIRE);
+        ++s->ring_read;
+        if (slot >= s->max_jobs || s->slots[slot].state != kSlotActive)
+            return fail(NH_EDEVICE, "corrupt completion ring entry %u", slot);
+        ServerSlot &sl = s->slots[slot];
+        const uint32_t blocks = (uint32_t)((sl.n + 255) / 256);
+        k_resolve<<<blocks, 256, 0, s->stream>>>(s->d_jobs, s->d_js, s->lin, (uint32_t)sl.lin_base,
+                                                  (uint32_t)(sl.lin_base + sl.n));
+        k_finalize<<<1, 1, 0, s->stream>>>(s->d_jobs, s->d_js, slot, slot + 1);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(&s->js_h[slot], &s->d_js[slot], sizeof(JobState), hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipEventRecord(sl.ev, s->stream));
+        sl.state = kSlotResolving;
+        --s->active;
+        ++s->resolving;
+    }
+    // (b) resolved jobs: report, free their slots and ranges
+    if (s->resolving) {
+        for (uint32_t k = 0; k < s->max_jobs; ++k) {
+            ServerSlot &sl = s->slots[k];
+            if (sl.state != kSlotResolving) continue;
+            const hipError_t q = hipEventQuery(sl.ev);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) return fail(NH_EDEVICE, "job event failed: %s", hipGetErrorString(q));
+            const JobState &js = s->js_h[k];
+            nh_completion c{};
+            c.tag = sl.tag;
+            c.status = (js.flags & kJobBadSample) ? NH_EINVAL : NH_OK;
+            c.rounds = js.done_round > js.start_round ? js.done_round - js.start_round : 0;
+            c.richness = js.rich_count;
+            c.events = js.events;
+            c.lineages = sl.n;
+            c.speciated = js.speciated;
+            c.merged = js.merged;
+            s->done.push_back(c);
+            if (sl.n) s->lin_alloc.release(sl.lin_base, sl.n);
+            s->rich_alloc.release(sl.rich_base, sl.rich_slots);
+            sl.state = kSlotFree;
+            s->free_slots.push_back(k);
+            --s->resolving;
+        }
+    }
+    // (c) admission: FIFO, with backfill over `lookahead` jobs behind a head that does not fit
+    size_t k = 0;
+    uint32_t skipped = 0;
+    while (k < s->pending.size() && !s->free_slots.empty()) {
+        bool admitted = false;
+        if (int rc = server_admit(s, s->pending[k].first, s->pending[k].second, admitted)) return rc;
+        if (admitted) {
+            s->pending.erase(s->pending.begin() + (long)k);
+        } else {
+            if (++skipped > s->lookahead) break;
+            ++k;
+        }
+    }
+    // (d) rounds: keep two launches in flight while jobs are active
+    if (s->active) {
+        const unsigned long long word = __atomic_load_n(s->status_h, __ATOMIC_ACQUIRE);
+        if ((word >> 31) & 1u) return fail(NH_EDEVICE, "kernel reported an error");
+        const uint32_t next_round = (uint32_t)(word >> 32);
+        const uint64_t completed = next_round >= 1 ? next_round - 1 : 0;
+        while (s->rounds_enqueued < completed + 2ull * s->cfg.rounds_per_graph)
+            if (int rc = server_launch_round(s)) return rc;
+    }
+    if (active_out) *active_out = s->active + s->resolving;
+    if (pending_out) *pending_out = (uint32_t)s->pending.size();
+    return NH_OK;
+}
+
+NH_API int nh_server_poll(nh_server *s, nh_completion *out, uint32_t max, uint32_t *n_out) {
+    if (!s || (!out && max)) return fail(NH_EINVAL, "NULL server or output");
+    const uint32_t n = (uint32_t)std::min<size_t>(max, s->done.size());
+    for (uint32_t k = 0; k < n; ++k) out[k] = s->done[k];
+    s->done.erase(s->done.begin(), s->done.begin() + n);
+    if (n_out) *n_out = n;
+    return NH_OK;
+}
+
+NH_API int nh_server_drain(nh_server *s, double timeout_s) {
+    if (!s) return fail(NH_EINVAL, "NULL server");
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint64_t spin = 0;; ++spin) {
+        uint32_t act = 0, pend = 0;
+        if (int rc = nh_server_progress(s, &act, &pend)) return rc;
+        if (act == 0 && pend == 0) return NH_OK;
+        if ((spin & 255) == 0) {
+            if (std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > timeout_s)
+                return fail(NH_ETIMEOUT, "drain exceeded %.1f s (%u active, %u queued)", timeout_s, act, pend);
+            std::this_thread::yield();
+        }
+    }
+}
+
+NH_API void nh_server_destroy(nh_server *s) { server_free(s); }

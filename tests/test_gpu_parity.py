@@ -1,0 +1,289 @@
+"""GPU parity: species identities from the HIP library (through the C ABI)
+must equal the CPU oracle's bit for bit, on the same seeded inputs.
+
+Small and ragged cases are compared in full; the full-size workloads are
+compared in full where the culled oracle is fast (configs 1 and 2) and on
+uniformly sampled outputs traced one by one otherwise (configs 3 and 4),
+together with properties that hold at any size (richness = distinct ids,
+duplicates agree, results independent of batching and tuning)."""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2108_05815_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-parity]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_2108_05815_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    return torch
+
+
+def _run(B, wl, seed, samples=None):
+    scn = B.Scenario.from_workload(wl)
+    s = wl.samples if samples is None else samples
+    return B.simulate(scn, seed, s)
+
+
+# --------------------------------------------------------------------------- #
+# Config 1: non-spatial J = 1000, nu = 0.1, 1000 seeds                        #
+# --------------------------------------------------------------------------- #
+
+def test_config1_all_seeds_batched_and_plain(B, torch_mod):
+    torch = torch_mod
+    wl = W.config1(1000)
+    osc = oracle.Scenario(wl.capacity, wl.weights, wl.nu)
+    scn = B.Scenario.from_workload(wl)
+    dev = torch.device("cuda:0")
+    samples = torch.from_numpy(wl.samples.astype(np.int64)).to(dev)
+    outs = [torch.empty(len(wl.samples), dtype=torch.int64, device=dev) for _ in wl.seeds]
+    rich = torch.zeros(len(wl.seeds), dtype=torch.int64, device=dev)
+    jobs = [(scn, seed, samples, outs[k], rich[k:k + 1]) for k, seed in enumerate(wl.seeds)]
+    ws = torch.empty(B.workspace_bytes(len(wl.samples) * len(wl.seeds), len(jobs)), dtype=torch.uint8, device=dev)
+    say("config 1: 1000 seeds in one batch")
+    stats = B.batch_run(jobs, ws)
+    torch.cuda.synchronize()
+    got_rich = rich.cpu().numpy()
+    richs = []
+    for k, seed in enumerate(wl.seeds):
+        ref, _, _ = osc.simulate_naive(seed, wl.samples)
+        got = outs[k].cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, ref), f"seed {seed}"
+        r = oracle.richness(ref)
+        assert got_rich[k] == r and stats[k]["richness"] == r
+        richs.append(r)
+    # the GPU results obey the closed form too (Ewens mean, theta = J nu / (1 - nu))
+    th = 1000 * 0.1 / 0.9
+    expected = sum(th / (th + i) for i in range(1000))
+    richs = np.array(richs, float)
+    assert abs(richs.mean() - expected) < 4 * richs.std(ddof=1) / np.sqrt(len(richs))
+    say("config 1: plain form, 25 seeds")
+    for seed in range(25):
+        got, r, st = B.simulate(scn, seed, wl.samples)
+        assert np.array_equal(got, outs[seed].cpu().numpy().view(np.uint64))
+        assert r == got_rich[seed] and st["lineages"] == 1000
+
+
+# --------------------------------------------------------------------------- #
+# Small and ragged workloads, compared in full                                 #
+# --------------------------------------------------------------------------- #
+
+SMALL = [
+    W.nonspatial(300, 0.05, [4], name="nonspatial J=300"),
+    W.nonspatial(1, 0.01, [5], name="nonspatial J=1"),
+    W.spatial_torus(24, 2, 1.5, 4, 0.02, [5], name="torus 24x24 cap2 R4"),
+    W.spatial_torus(37, 3, 2.5, 9, 0.004, [6], name="torus 37x37 cap3 R9"),
+    W.Workload("fractal 24 per-deme", W.fractal_capacity(24, 11, base_period=8), W.gaussian_kernel(2.0, 5), 0.02, 1,
+               None, [6]),
+    W.Workload("fractal 61 per-deme", W.fractal_capacity(61, 12, base_period=16), W.gaussian_kernel(3.0, 8), 0.003,
+               1, None, [2**64 - 1]),
+    W.Workload("3x3 cap1 flat", np.ones((3, 3), np.uint32), np.ones((3, 3)), 0.1, 0, None, [0]),
+    W.spatial_torus(16, 1, 1.0, 0, 0.05, [7], name="no dispersal"),
+    W.spatial_torus(20, 2, 1.0, 2, 1.0, [8], name="nu = 1"),
+]
+
+
+@pytest.mark.parametrize("wl", SMALL, ids=[w.name for w in SMALL])
+def test_small_workloads_full(B, wl):
+    osc = oracle.Scenario(wl.capacity, wl.weights, wl.nu, mode=wl.mode)
+    samples = np.arange(osc.individuals, dtype=np.uint64)
+    seed = wl.seeds[0]
+    say(wl.name, "n =", len(samples))
+    ref, _, _ = osc.simulate_culled(seed, samples, 2.0)
+    got, rich, st = _run(B, wl, seed, samples)
+    assert np.array_equal(got, ref)
+    assert rich == oracle.richness(ref) == st["richness"]
+    assert st["speciated"] + st["merged"] == len(samples)
+    # the same through device buffers, every round in 8-lanes-per-lineage groups, and one lane per lineage
+    import torch
+    dev = torch.device("cuda:0")
+    scn = B.Scenario.from_workload(wl)
+    d_s = torch.from_numpy(samples.astype(np.int64)).to(dev)
+    ws = torch.empty(B.workspace_bytes(len(samples), 1), dtype=torch.uint8, device=dev)
+    for coop in (1 << 30, 1):
+        out = torch.empty(len(samples), dtype=torch.int64, device=dev)
+        st2 = B.batch_run([(scn, seed, d_s, out, None)], ws, B.make_config(coop_max=coop))[0]
+        assert np.array_equal(out.cpu().numpy().view(np.uint64), ref), coop
+        assert st2["events"] == st["events"] or coop == 1
+
+
+def test_subsets_permutations_duplicates(B):
+    wl = SMALL[3]
+    scn = B.Scenario.from_workload(wl)
+    osc = oracle.Scenario(wl.capacity, wl.weights, wl.nu)
+    n = osc.individuals
+    full, _, _ = B.simulate(scn, 9, np.arange(n, dtype=np.uint64))
+    rng = np.random.default_rng(1)
+    for size in (1, 2, 63, 64, 65, 1000, 5000):
+        sub = rng.choice(n, size=size, replace=True).astype(np.uint64)
+        say("subset", size)
+        got, rich, _ = B.simulate(scn, 9, sub)
+        assert np.array_equal(got, full[sub.astype(np.int64)])
+        assert rich == len(np.unique(got))
+    ref, _, _ = osc.simulate_naive(9, np.arange(0, n, 97, dtype=np.uint64))
+    assert np.array_equal(full[::97], ref)
+
+
+def test_empty_sample_list(B):
+    scn = B.Scenario.from_workload(SMALL[0])
+    got, rich, st = B.simulate(scn, 1, np.zeros(0, np.uint64))
+    assert got.shape == (0,) and rich == 0
+
+
+def test_rejects_out_of_range_sample_on_device(B, torch_mod):
+    torch = torch_mod
+    wl = SMALL[2]
+    scn = B.Scenario.from_workload(wl)
+    dev = torch.device("cuda:0")
+    bad = torch.tensor([0, 5, scn.individuals], dtype=torch.int64, device=dev)
+    out = torch.empty(3, dtype=torch.int64, device=dev)
+    ws = torch.empty(B.workspace_bytes(3, 1), dtype=torch.uint8, device=dev)
+    with pytest.raises(B.NecsimError) as e:
+        B.batch_run([(scn, 1, bad, out, None)], ws)
+    assert e.value.code == B.NH_EINVAL
+    # the library is still usable afterwards
+    got, _, _ = B.simulate(scn, 1, np.array([0, 5], np.uint64))
+    ref, _, _ = oracle.Scenario(wl.capacity, wl.weights, wl.nu).simulate_naive(1, np.array([0, 5], np.uint64))
+    assert np.array_equal(got, ref)
+
+
+def test_rejects_small_workspace(B, torch_mod):
+    torch = torch_mod
+    scn = B.Scenario.from_workload(SMALL[0])
+    dev = torch.device("cuda:0")
+    s = torch.arange(10, dtype=torch.int64, device=dev)
+    out = torch.empty(10, dtype=torch.int64, device=dev)
+    ws = torch.empty(B.workspace_bytes(10, 1) - 256, dtype=torch.uint8, device=dev)
+    with pytest.raises(B.NecsimError) as e:
+        B.batch_run([(scn, 1, s, out, None)], ws)
+    assert e.value.code == B.NH_ENOMEM
+
+
+# --------------------------------------------------------------------------- #
+# Config 2: 256 x 256 torus, 65,536 lineages, compared in full                 #
+# --------------------------------------------------------------------------- #
+
+def test_config2_full_bitexact(B):
+    wl = W.config2(seeds=(42, 43, 44))
+    scn = B.Scenario.from_workload(wl)
+    osc = oracle.Scenario(wl.capacity, wl.weights, wl.nu)
+    for seed in wl.seeds:
+        say("config 2 seed", seed)
+        got, rich, st = B.simulate(scn, seed, wl.samples)
+        ref, ev, _ = osc.simulate_culled(seed, wl.samples, 1.0)
+        assert np.array_equal(got, ref)
+        assert rich == oracle.richness(ref)
+        assert st["speciated"] + st["merged"] == 65536
+
+
+def test_tuning_never_changes_results(B, torch_mod):
+    """Horizon schedule, block size, occupancy, graph length and the lanes-per-lineage switch are
+    performance knobs only."""
+    torch = torch_mod
+    wl = W.config2()
+    scn = B.Scenario.from_workload(wl)
+    dev = torch.device("cuda:0")
+    samples = torch.from_numpy(wl.samples.astype(np.int64)).to(dev)
+    ws = torch.empty(B.workspace_bytes(len(wl.samples), 1), dtype=torch.uint8, device=dev)
+    base = None
+    for cfg in (dict(), dict(horizon0=0.125, horizon_growth=1.05), dict(horizon0=8.0, horizon_growth=2.0),
+                dict(block_size=64, blocks_per_cu=1, rounds_per_graph=1), dict(block_size=128, blocks_per_cu=8),
+                dict(horizon_step_max=1.0, rounds_per_graph=32), dict(coop_max=1), dict(coop_max=1 << 30),
+                dict(coop_max=1 << 30, block_size=64, horizon0=2.0)):
+        say("config 2 tuning", cfg)
+        out = torch.empty(len(wl.samples), dtype=torch.int64, device=dev)
+        B.batch_run([(scn, 42, samples, out, None)], ws, B.make_config(**cfg))
+        got = out.cpu().numpy()
+        if base is None:
+            base = got
+        assert np.array_equal(got, base)
+
+
+def test_repeat_runs_are_identical(B):
+    wl = W.config2()
+    scn = B.Scenario.from_workload(wl)
+    a, ra, sa = B.simulate(scn, 7, wl.samples)
+    b, rb, sb = B.simulate(scn, 7, wl.samples[::-1].copy())
+    assert np.array_equal(a, b[::-1]) and ra == rb
+    assert sa["events"] == sb["events"]
+
+
+# --------------------------------------------------------------------------- #
+# Config 3: 1024 x 1024 fractal habitat, per-deme tables, sampled outputs       #
+# --------------------------------------------------------------------------- #
+
+def test_config3_full_size_sampled(B):
+    wl = W.config3()
+    say("config 3: building per-deme tables")
+    t0 = time.time()
+    scn = B.Scenario.from_workload(wl)
+    say(f"config 3: tables {scn.table_bytes / 2**30:.2f} GiB in {time.time() - t0:.1f} s; simulating", len(wl.samples))
+    got, rich, st = B.simulate(scn, wl.seeds[0], wl.samples)
+    say("config 3:", st)
+    assert rich == len(np.unique(got))
+    assert st["speciated"] + st["merged"] == len(wl.samples)
+    osc = oracle.Scenario(wl.capacity, wl.weights, wl.nu, mode=1)
+    pick = np.random.default_rng(3).choice(len(wl.samples), size=10, replace=False)
+    say("config 3: oracle traces of", len(pick), "samples")
+    ref, _, ev = osc.simulate_naive(wl.seeds[0], wl.samples[pick])
+    assert np.array_equal(got[pick], ref), (got[pick], ref)
+
+
+# --------------------------------------------------------------------------- #
+# Config 4: 256 scenarios in one batch                                         #
+# --------------------------------------------------------------------------- #
+
+def test_config4_batch_sampled_and_alone_equals_mix(B, torch_mod):
+    torch = torch_mod
+    wls = W.config4()
+    dev = torch.device("cuda:0")
+    say("config 4: creating 256 scenarios")
+    scns = [B.Scenario.from_workload(w) for w in wls]
+    samples = [torch.from_numpy(w.samples.astype(np.int64)).to(dev) for w in wls]
+    outs = [torch.empty(len(w.samples), dtype=torch.int64, device=dev) for w in wls]
+    rich = torch.zeros(len(wls), dtype=torch.int64, device=dev)
+    jobs = [(scns[k], wls[k].seeds[0], samples[k], outs[k], rich[k:k + 1]) for k in range(len(wls))]
+    n_total = sum(len(w.samples) for w in wls)
+    ws = torch.empty(B.workspace_bytes(n_total, len(jobs)), dtype=torch.uint8, device=dev)
+    say("config 4: batch run of", n_total, "lineages")
+    t0 = time.time()
+    stats = B.batch_run(jobs, ws)
+    torch.cuda.synchronize()
+    say(f"config 4: {time.time() - t0:.2f} s, events {sum(s['events'] for s in stats)}")
+    got_rich = rich.cpu().numpy()
+    rng = np.random.default_rng(4)
+    budget_events = 0
+    for k, w in enumerate(wls):
+        got = outs[k].cpu().numpy().view(np.uint64)
+        assert got_rich[k] == len(np.unique(got)) == stats[k]["richness"]
+        osc = oracle.Scenario(w.capacity, w.weights, w.nu)
+        m = 2 if w.nu >= 1e-4 else 1
+        pick = rng.choice(len(w.samples), size=m, replace=False)
+        ref, _, ev = osc.simulate_naive(w.seeds[0], w.samples[pick])
+        budget_events += int(ev.sum())
+        assert np.array_equal(got[pick], ref), (k, w.name)
+    say("config 4: oracle traced events", budget_events)
+    # batch-alone == batch-mix for a few scenarios of different sizes
+    for k in (0, 1, 2, int(np.argmin([w.individuals for w in wls]))):
+        say("config 4 alone:", wls[k].name)
+        alone, r, _ = B.simulate(scns[k], wls[k].seeds[0], wls[k].samples)
+        assert np.array_equal(alone, outs[k].cpu().numpy().view(np.uint64))
+        assert r == got_rich[k]

@@ -1,0 +1,111 @@
+"""GPU tests of the continuous-batching engine (nh_server_*): jobs submitted while others
+run are admitted as lineage slots free up, and each result is bitwise the same as the
+job run alone (and as the oracle)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2108_05815_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-serving]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2108_05815_amd import binding as B
+    return B, torch
+
+
+def _mix():
+    wl = [W.nonspatial(1000, 0.1, [s], name=f"C1 seed {s}") for s in range(6)]
+    wl += [W.spatial_torus(24, 2, 1.5, 4, 0.02, [5], name="torus 24"),
+           W.spatial_torus(37, 3, 2.5, 9, 0.004, [6], name="torus 37"),
+           W.Workload("fractal 61", W.fractal_capacity(61, 12, base_period=16), W.gaussian_kernel(3.0, 8), 0.003, 1,
+                      None, [2**63 + 11]),
+           W.nonspatial(20000, 1e-3, [77], name="nonspatial J=20000"),
+           W.spatial_torus(64, 1, 2.0, 10, 1e-3, [8], name="torus 64 C2-like")]
+    for w in wl:
+        if w.samples is None:
+            w.samples = np.arange(int(w.capacity.astype(np.uint64).sum()), dtype=np.uint64)
+    return wl
+
+
+def test_served_results_equal_alone_and_oracle(env):
+    B, torch = env
+    dev = torch.device("cuda:0")
+    wls = _mix()
+    scns = [B.Scenario.from_workload(w) for w in wls]
+    biggest = max(len(w.samples) for w in wls)
+    # a pool that holds the biggest job but not everything at once: admissions must wait
+    srv = B.Server(lineage_capacity=biggest + 3000, max_jobs=8, lookahead=4)
+    outs, submitted = {}, 0
+    order = list(range(len(wls)))
+    done = {}
+    step = 0
+    while len(done) < len(wls):
+        # stagger: submit one more job every few progress calls
+        if submitted < len(order) and step % 3 == 0:
+            k = order[submitted]
+            s = torch.from_numpy(wls[k].samples.astype(np.int64)).to(dev)
+            o = torch.empty(len(wls[k].samples), dtype=torch.int64, device=dev)
+            r = torch.zeros(1, dtype=torch.int64, device=dev)
+            srv.submit(k, scns[k], wls[k].seeds[0], s, o, r)
+            outs[k] = (o, r)
+            submitted += 1
+        srv.progress()
+        for c in srv.poll():
+            done[c["tag"]] = c
+        step += 1
+        assert step < 10_000_000
+    srv.drain(60.0)
+    for k, w in enumerate(wls):
+        c = done[k]
+        assert c["status"] == 0 and c["lineages"] == len(w.samples)
+        got = outs[k][0].cpu().numpy().view(np.uint64)
+        alone, rich, _ = B.simulate(scns[k], w.seeds[0], w.samples)
+        assert np.array_equal(got, alone), w.name
+        assert int(outs[k][1].item()) == rich == c["richness"]
+        say(w.name, "rounds", c["rounds"], "richness", rich)
+    # oracle on the small ones
+    for k in (0, 6, 8):
+        w = wls[k]
+        ref, _, _ = oracle.Scenario(w.capacity, w.weights, w.nu, mode=w.mode).simulate_culled(w.seeds[0], w.samples,
+                                                                                              2.0)
+        assert np.array_equal(outs[k][0].cpu().numpy().view(np.uint64), ref), w.name
+    srv.close()
+
+
+def test_server_isolates_bad_and_empty_jobs(env):
+    B, torch = env
+    dev = torch.device("cuda:0")
+    w = W.spatial_torus(24, 2, 1.5, 4, 0.02, [5])
+    scn = B.Scenario.from_workload(w)
+    srv = B.Server(lineage_capacity=10_000, max_jobs=4)
+    good = torch.from_numpy(w.samples.astype(np.int64)).to(dev)
+    out_good = torch.empty(len(w.samples), dtype=torch.int64, device=dev)
+    bad = torch.tensor([0, scn.individuals + 5, 3], dtype=torch.int64, device=dev)
+    out_bad = torch.empty(3, dtype=torch.int64, device=dev)
+    empty = torch.zeros(0, dtype=torch.int64, device=dev)
+    out_empty = torch.zeros(0, dtype=torch.int64, device=dev)
+    rich_empty = torch.full((1,), 7, dtype=torch.int64, device=dev)
+    srv.submit(1, scn, 5, good, out_good)
+    srv.submit(2, scn, 5, bad, out_bad)
+    srv.submit(3, scn, 5, empty, out_empty, rich_empty)
+    srv.drain(60.0)
+    res = {c["tag"]: c for c in srv.poll()}
+    assert res[1]["status"] == 0 and res[2]["status"] == B.NH_EINVAL and res[3]["status"] == 0
+    assert int(rich_empty.item()) == 0 and res[3]["richness"] == 0
+    alone, _, _ = B.simulate(scn, 5, w.samples)
+    assert np.array_equal(out_good.cpu().numpy().view(np.uint64), alone)
+    with pytest.raises(B.NecsimError):
+        too_big = torch.zeros(20_000, dtype=torch.int64, device=dev)
+        srv.submit(9, scn, 5, too_big, torch.empty(20_000, dtype=torch.int64, device=dev))
+    srv.close()

@@ -1,0 +1,95 @@
+"""Host-only checks of the C-ABI library: it loads, exports every symbol the
+header declares, and rejects invalid scenarios before touching the GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "necsim_hip.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nh_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2108_05815_amd import binding
+    return binding
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("nh_scenario_create", "nh_scenario_destroy", "nh_batch_run", "nh_simulate",
+                     "nh_simulate_device", "nh_last_error", "nh_workspace_bytes", "nh_scenario_footprint_bytes"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(B):
+    lib = C.CDLL(B.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert set(_declared()) == set(B.EXPORTED)
+    assert b"gfx950" in B.nh_version()
+
+
+def test_workspace_sizes_grow_with_the_batch(B):
+    a = B.workspace_bytes(1000, 1)
+    b = B.workspace_bytes(2000, 1)
+    c = B.workspace_bytes(2000, 64)
+    assert 0 < a < b < c
+    assert B.workspace_bytes(0, 1) > 0
+
+
+@pytest.mark.parametrize("kwargs,msg", [
+    (dict(nu=0.0), "nu"),
+    (dict(nu=1.5), "nu"),
+    (dict(nu=float("nan")), "nu"),
+    (dict(dt=3.0), "delta_t"),
+    (dict(dt=-1.0), "delta_t"),
+    (dict(lam=0.0), "lambda"),
+    (dict(lam=float("inf")), "lambda"),
+    (dict(lam=4096.0, dt=512.0), "2^20"),
+])
+def test_scenario_parameter_validation(B, kwargs, msg):
+    nu = kwargs.pop("nu", 0.1)
+    with pytest.raises(B.NecsimError) as e:
+        B.Scenario(np.ones((8, 8), np.uint32), np.ones((3, 3)), nu, **kwargs)
+    assert e.value.code == B.NH_EINVAL
+    assert msg in str(e.value)
+
+
+def test_scenario_shape_validation(B):
+    with pytest.raises(B.NecsimError):
+        B.Scenario(np.ones((4, 4), np.uint32), np.ones((5, 5)), 0.1)  # 2R+1 > W
+    with pytest.raises(B.NecsimError):
+        B.Scenario(np.zeros((4, 4), np.uint32), np.ones((3, 3)), 0.1, mode=1)  # nothing habitable
+    cap = np.ones((4, 4), np.uint32)
+    cap[1, 2] = 0
+    with pytest.raises(B.NecsimError):
+        B.Scenario(cap, np.ones((3, 3)), 0.1, mode=0)  # shared table with an empty deme
+    w = np.ones((3, 3))
+    w[0, 0] = -1.0
+    with pytest.raises(B.NecsimError):
+        B.Scenario(np.ones((4, 4), np.uint32), w, 0.1)
+    with pytest.raises(B.NecsimError):
+        B.Scenario(np.ones((4, 4), np.uint32), np.zeros((3, 3)), 0.1)
+    big = np.full((1 << 10, 1 << 10), 1 << 12, np.uint32)
+    with pytest.raises(B.NecsimError) as e:
+        B.Scenario(big, np.ones((1, 1)), 0.1)
+    assert "2^32" in str(e.value)
+
+
+def test_isolated_deme_in_per_deme_mode_is_rejected(B):
+    cap = np.zeros((9, 9), np.uint32)
+    cap[4, 4] = 3
+    w = np.ones((3, 3))
+    w[1, 1] = 0.0  # no self-dispersal and no habitable neighbour
+    with pytest.raises(B.NecsimError) as e:
+        B.Scenario(cap, w, 0.1, mode=1)
+    assert "habitable mass" in str(e.value)
