@@ -9,9 +9,14 @@ richness -- every kernel of the path, on inputs already resident in HBM.  The
 scenario tables are built once (they are the scenario, like model weights);
 each step uses its own seed.
 
-Prints one JSON line: lineage events/s (value), individuals/s, the round
-kernel's VALU roofline fraction (HIP events on the library's stream), and the
-CPU oracle timed on a bounded sample of the same workload.
+Before timing, the round kernels' performance knobs are autotuned on this
+workload (results never depend on them).  Prints one JSON line: lineage
+events/s (value), individuals/s, the round kernel's VALU roofline fraction (HIP
+events on the library's stream), the batched form (the 256-scenario mix in one
+run vs one scenario per run), the served form (a Poisson request stream through
+the continuous-batching server: p50/p99 latency and throughput, vs the same
+requests one per run), and the CPU oracle timed on a bounded sample of the
+plain workload.
 """
 from __future__ import annotations
 
@@ -38,6 +43,13 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_round_c2_traffic.json"),
                     help="HBM bytes per round launch from rocprofv3 FETCH_SIZE/WRITE_SIZE runs")
+    ap.add_argument("--no-tune", action="store_true", help="use the library defaults instead of autotuning")
+    ap.add_argument("--knobs", default=None, help="JSON dict of tuned knobs to use instead of autotuning")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched (C4) and served (C5) forms")
+    ap.add_argument("--batch-plain-subset", type=int, default=32,
+                    help="scenarios of the 256-scenario mix also run one per launch for the comparison")
+    ap.add_argument("--serve-seconds", type=float, default=5.0, help="length of the served request stream")
+    ap.add_argument("--serve-plain", type=int, default=48, help="requests of the stream also run one per launch")
     return ap.parse_args()
 
 
@@ -82,8 +94,23 @@ def main():
     out = torch.empty(n, dtype=torch.int64, device=dev)
     rich = torch.zeros(1, dtype=torch.int64, device=dev)
     ws = torch.empty(B.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
-    cfg = B.make_config(event_timing=1)
     stream = torch.cuda.current_stream()
+    tuned = None
+    if args.knobs:
+        from paper_2108_05815_amd import autotune as AT
+        tuned = json.loads(args.knobs)
+        cfg = AT.to_config(tuned, event_timing=1)
+    elif not args.no_tune:
+        from paper_2108_05815_amd import autotune as AT
+
+        def one(cfg):
+            st = B.batch_run([(scn, 7, samples, out, rich)], ws, cfg, stream)[0]
+            return st["device_ms"] / 1e3
+
+        tuned, tuned_s, _ = AT.tune(one, reps=2)
+        cfg = AT.to_config(tuned, event_timing=1)
+    else:
+        cfg = B.make_config(event_timing=1)
 
     for k in range(args.warmup):
         B.batch_run([(scn, 1000 + k, samples, out, rich)], ws, cfg, stream)
@@ -122,7 +149,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "form": "plain (one scenario per run)", "lineages": n, "torus": "256x256",
                    "capacity": 1, "sigma": 2.0, "kernel": "21x21", "nu": wl.nu, "lambda": 1.0, "delta_t": 1.0,
-                   "seeds": f"42..{41 + args.steps}"},
+                   "seeds": f"42..{41 + args.steps}", "tuned": tuned},
         "individuals_per_s": args.steps * n / elapsed,
         "events_per_step": totals["events"] / args.steps,
         "mean_richness": totals["richness"] / args.steps,
@@ -142,9 +169,80 @@ def main():
             "draws_per_event": totals["exp_draws"] / max(1, totals["events"]),
         },
     }
+    if not args.no_extras:
+        line["batched"] = batched_form(args, B, W, torch)
+        line["serve"] = served_form(args, W, torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def batched_form(args, B, W, torch) -> dict:
+    """The 256-scenario mix in one batched run, against one scenario per run on a subset."""
+    dev = torch.device("cuda:0")
+    wls = W.config4()
+    scns = [B.Scenario.from_workload(w) for w in wls]
+    samples = [torch.from_numpy(w.samples.astype(np.int64)).to(dev) for w in wls]
+    outs = [torch.empty(len(w.samples), dtype=torch.int64, device=dev) for w in wls]
+    n_total = sum(len(w.samples) for w in wls)
+    ws = torch.empty(B.workspace_bytes(n_total, len(wls)), dtype=torch.uint8, device=dev)
+    jobs = [(scns[k], wls[k].seeds[0], samples[k], outs[k], None) for k in range(len(wls))]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = B.batch_run(jobs, ws)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ev = sum(x["events"] for x in st)
+    m = min(args.batch_plain_subset, len(wls))
+    sub = jobs[:m]
+    n_sub = sum(len(w.samples) for w in wls[:m])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_b = B.batch_run(sub, ws)
+    torch.cuda.synchronize()
+    el_b = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ev_p = 0
+    for j in sub:
+        ev_p += B.batch_run([j], ws)[0]["events"]
+    torch.cuda.synchronize()
+    el_p = time.perf_counter() - t0
+    ev_b = sum(x["events"] for x in st_b)
+    return {"workload": "C4 mix: 256 scenarios, sides 64-512, capacity 1-4, sigma 1-6, nu 1e-6..1e-2",
+            "lineages": n_total, "seconds": el, "events_per_s": ev / el, "individuals_per_s": n_total / el,
+            "rounds": st[0]["rounds"],
+            "subset": {"scenarios": m, "lineages": n_sub, "batched_s": el_b, "plain_s": el_p,
+                       "batched_events_per_s": ev_b / el_b, "plain_events_per_s": ev_p / el_p,
+                       "speedup": el_p / el_b}}
+
+
+def served_form(args, W, torch) -> dict:
+    """Poisson request stream (200 req/s) through the continuous-batching server, and its first
+    requests one per run for comparison."""
+    from paper_2108_05815_amd import serve as S
+    arrivals, specs = W.config5_requests(duration=args.serve_seconds)
+    served = S.run_served(arrivals, specs, hbm_budget_bytes=64 << 30)
+    m = min(args.serve_plain, len(specs))
+    plain = S.run_plain(arrivals[:m], specs[:m])
+    prefix = served["latencies_s"][:m]
+    ev_prefix = None
+    out = {"workload": f"C5: Poisson 200 req/s for {args.serve_seconds:g} s, half spatial (C4-like), half "
+                       "non-spatial J 1e3..1e6, all individuals sampled",
+           "requests": served["requests"], "p50_ms": served["latency"]["p50_ms"],
+           "p99_ms": served["latency"]["p99_ms"], "max_ms": served["latency"]["max_ms"],
+           "events_per_s": served["events_per_s"], "individuals_per_s": served["individuals_per_s"],
+           "offered_requests_per_s": served["offered_requests_per_s"], "sustained": served["sustained"],
+           "median_latency_first_third_ms": served["median_latency_first_third_ms"],
+           "median_latency_last_third_ms": served["median_latency_last_third_ms"],
+           "lineage_capacity": served["lineage_capacity"],
+           "peak_pending": served["peak_pending"], "peak_active": served["peak_active"],
+           "plain_prefix": {"requests": m, "plain_p50_ms": plain["latency"]["p50_ms"],
+                            "plain_p99_ms": plain["latency"]["p99_ms"],
+                            "plain_events_per_s": plain["events_per_s"],
+                            "served_p50_ms": float(np.percentile(prefix, 50) * 1e3),
+                            "served_p99_ms": float(np.percentile(prefix, 99) * 1e3)}}
+    del ev_prefix
+    return out
 
 
 if __name__ == "__main__":

@@ -95,7 +95,9 @@ typedef struct {
     uint32_t rounds_per_graph; /* round kernels per captured graph (1 = plain launches), default 8 */
     uint32_t event_timing; /* 1: bracket every round launch with HIP events (fills round_kernel_ms) */
     uint32_t coop_max;    /* queues shorter than this many lineages run 8 lanes per lineage; default
-                             (0): a launch's lane count / 8 + 1; 1 keeps one lane per lineage always */
+                             (0): a launch's lane count / 16 + 1; 1 keeps one lane per lineage always */
+    uint32_t table_placement; /* 0: stage a shared dispersal table in LDS for single-job runs when it
+                                 fits (4096 entries); 1: read every table from global memory */
     double timeout_s;     /* wall-clock limit of one run, default 600 */
 } nh_config;
 

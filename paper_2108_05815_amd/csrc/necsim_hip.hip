@@ -249,8 +249,8 @@ __device__ __forceinline__ double log_u53o(uint64_t r) {
 // the first sum strictly beyond t_last is the answer.  Returns a negative
 // value (and flags the run) only if the search runs away, which needs a
 // broken scenario.
-__device__ __forceinline__ double next_event_time(const JobView &v, uint32_t loc, double t_last, uint32_t *err,
-                                                  Counters &cnt) {
+__device__ __forceinline__ double next_event_time_wide(const JobView &v, uint32_t loc, double t_last, uint32_t *err,
+                                                       Counters &cnt) {
     uint64_t k = (uint64_t)floor(t_last * v.inv_dt);
     double e = (double)k * v.dt;
     double end = (double)(k + 1) * v.dt;
@@ -274,6 +274,47 @@ __device__ __forceinline__ double next_event_time(const JobView &v, uint32_t loc
             k += 1;
             e = (double)k * v.dt;
             end = (double)(k + 1) * v.dt;
+            j = 0;
+            continue;
+        }
+        if (e > t_last) return e;
+        ++j;
+    }
+    atomicOr(err, kErrRunaway);
+    return -1.0;
+}
+
+// The same search for interval indices below 2^31 (every time below 2^31 dt):
+// the index is a u32, so its conversions are single instructions, and the
+// interval end is start + dt, which equals (k + 1) dt exactly because dt is a
+// power of two.  Bit-identical to next_event_time_wide.
+__device__ __forceinline__ double next_event_time(const JobView &v, uint32_t loc, double t_last, uint32_t *err,
+                                                  Counters &cnt) {
+    const double kf = floor(t_last * v.inv_dt);
+    if (!(kf < 2147483648.0)) return next_event_time_wide(v, loc, t_last, err, cnt);
+    uint32_t k = (uint32_t)kf;
+    double e = (double)k * v.dt;
+    double end = e + v.dt;
+    uint32_t j = 0;
+    uint64_t second = 0;
+    for (uint32_t guard = 0; guard < (1u << 24); ++guard) {
+        uint64_t r;
+        if ((j & 1u) == 0u) {
+            uint32_t c0 = loc, c1 = k, c2 = 0, c3 = j >> 1; // domain 0
+            philox10(c0, c1, c2, c3, v.key0, v.key1);
+            ++cnt.philox;
+            r = ((uint64_t)c1 << 32) | c0;
+            second = ((uint64_t)c3 << 32) | c2;
+        } else {
+            r = second;
+        }
+        const double x = (-log_u53o(r)) * v.inv_lambda;
+        ++cnt.draws;
+        e = e + x;
+        if (e >= end) {
+            k += 1;
+            e = end;
+            end = e + v.dt;
             j = 0;
             continue;
         }
@@ -454,59 +495,114 @@ __device__ __forceinline__ double shfl_f64(double x, int src) {
 // ---------------------------------------------------------------------------
 constexpr uint32_t kGroup = 8;
 
-// Next event time with lane gl of the group on interval k + gl (+ 8 per
-// extra batch).  Every lane takes the first draw of its interval on one common
-// code path.  Lane 0 of the first batch holds the interval containing t_last
-// and, when that first sum has neither left the interval nor passed t_last,
-// keeps walking exactly as next_event_time() does; every later interval
-// starts beyond t_last, so its first draw alone decides it (an event iff it
-// lands before the interval's end).  The answer is the hit of the lowest
-// interval.  Counters record the draws the one-lane search would have made.
+// Broadcast lane J of each quad (4 lanes) to the whole quad: two DPP moves.
+template <int J>
+__device__ __forceinline__ double quad_bcast(double x) {
+    constexpr int ctrl = J | (J << 2) | (J << 4) | (J << 6); // quad_perm [J,J,J,J]
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, ctrl, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), ctrl, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Next event time by a group of 8 lanes, bit-identical to next_event_time().
+// First pass: lanes 0-3 take draws 0-3 of the interval k holding t_last (two
+// Philox blocks, one per lane pair, and four logarithms in one pass), share
+// them by DPP and scan them in order; lanes 4-7 take the first draw of
+// intervals k+1 .. k+4, which start beyond t_last, so that draw alone decides
+// them (an event iff it lands before the interval's end).  The answer is the
+// hit of the lowest interval; interval k keeps walking on its own in the rare
+// case that four draws neither pass t_last nor leave it.  Later passes give
+// one interval to each lane.  Counters record what the one-lane search needs.
 __device__ __forceinline__ double next_event_time_group(const JobView &v, uint32_t loc, double t_last, uint32_t gl,
                                                         uint32_t grp_base, uint32_t *err, Counters &cnt) {
-    const uint64_t k0 = (uint64_t)floor(t_last * v.inv_dt);
-    for (uint32_t batch = 0; batch < (1u << 20); ++batch) {
-        const uint64_t k = k0 + (uint64_t)batch * kGroup + gl;
-        double e = (double)k * v.dt;
-        const double end = (double)(k + 1) * v.dt;
-        uint32_t c0 = loc, c1 = (uint32_t)k, c2 = (uint32_t)(k >> 32), c3 = 0; // domain 0, call 0
+    const double kf = floor(t_last * v.inv_dt);
+    if (!(kf < 2147483648.0)) { // every lane runs the one-lane search (same result); lane 0 counts
+        Counters dummy;
+        return next_event_time_wide(v, loc, t_last, err, gl == 0u ? cnt : dummy);
+    }
+    uint32_t k = (uint32_t)kf;
+    {
+        const bool q0 = gl < 4u;
+        const uint32_t kk = q0 ? k : k + (gl - 3u);
+        uint32_t c0 = loc, c1 = kk, c2 = 0, c3 = q0 ? (gl >> 1) : 0u;
         philox10(c0, c1, c2, c3, v.key0, v.key1);
-        uint64_t second = ((uint64_t)c3 << 32) | c2;
-        e = e + (-log_u53o(((uint64_t)c1 << 32) | c0)) * v.inv_lambda;
-        uint32_t my_philox = 1, my_draws = 1;
-        bool hit = e < end;
-        if (batch == 0 && gl == 0 && hit && !(e > t_last)) {
-            hit = false;
-            for (uint32_t j = 1; j < (1u << 24); ++j) {
-                uint64_t r;
-                if ((j & 1u) == 0u) {
-                    uint32_t d0 = loc, d1 = (uint32_t)k, d2 = (uint32_t)(k >> 32), d3 = j >> 1;
-                    philox10(d0, d1, d2, d3, v.key0, v.key1);
-                    ++my_philox;
-                    r = ((uint64_t)d1 << 32) | d0;
-                    second = ((uint64_t)d3 << 32) | d2;
-                } else {
-                    r = second;
-                }
-                ++my_draws;
-                e = e + (-log_u53o(r)) * v.inv_lambda;
-                if (e >= end) break;
-                if (e > t_last) {
-                    hit = true;
-                    break;
+        const uint64_t first = ((uint64_t)c1 << 32) | c0, second = ((uint64_t)c3 << 32) | c2;
+        const double x = (-log_u53o((q0 && (gl & 1u)) ? second : first)) * v.inv_lambda;
+        const double start = (double)kk * v.dt;
+        const double end = start + v.dt;
+        const double x0 = quad_bcast<0>(x), x1 = quad_bcast<1>(x), x2 = quad_bcast<2>(x), x3 = quad_bcast<3>(x);
+        bool hit = false;
+        double e_out = 0.0;
+        uint32_t draws_k = 0, philox_k = 0;
+        if (q0) {
+            // interval k, in the one-lane order: leave on e >= end, accept on e > t_last
+            int state = 0; // 0 undecided, 1 hit, 2 left
+            double e = start;
+            const double xs[4] = {x0, x1, x2, x3};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (state == 0) {
+                    e = e + xs[j];
+                    draws_k = (uint32_t)j + 1u;
+                    if (e >= end) state = 2;
+                    else if (e > t_last) state = 1;
                 }
             }
+            philox_k = (draws_k + 1u) >> 1;
+            if (state == 0) { // rare: keep walking interval k from draw 4
+                uint64_t sec = 0;
+                for (uint32_t j = 4; j < (1u << 24); ++j) {
+                    uint64_t r;
+                    if ((j & 1u) == 0u) {
+                        uint32_t d0 = loc, d1 = k, d2 = 0, d3 = j >> 1;
+                        philox10(d0, d1, d2, d3, v.key0, v.key1);
+                        ++philox_k;
+                        r = ((uint64_t)d1 << 32) | d0;
+                        sec = ((uint64_t)d3 << 32) | d2;
+                    } else {
+                        r = sec;
+                    }
+                    ++draws_k;
+                    e = e + (-log_u53o(r)) * v.inv_lambda;
+                    if (e >= end) {
+                        state = 2;
+                        break;
+                    }
+                    if (e > t_last) {
+                        state = 1;
+                        break;
+                    }
+                }
+            }
+            hit = state == 1 && gl == 0u;
+            e_out = e;
+        } else {
+            e_out = start + x;
+            hit = e_out < end;
         }
         const uint32_t hits = (uint32_t)((__ballot(hit) >> grp_base) & 0xFFu);
-        const uint32_t upto = hits ? (uint32_t)(__ffs(hits) - 1) : kGroup - 1; // last interval consumed
-        if (gl == 0) { // lane 0's own draws plus one block and one draw per later interval consumed
-            if (batch == 0) {
-                cnt.philox += my_philox + upto;
-                cnt.draws += my_draws + upto;
-            } else {
-                cnt.philox += upto + 1;
-                cnt.draws += upto + 1;
-            }
+        if (gl == 0u) {
+            const uint32_t later = hits ? (hits & 1u ? 0u : (uint32_t)(__ffs(hits) - 1) - 3u) : 4u;
+            cnt.philox += philox_k + later;
+            cnt.draws += draws_k + later;
+        }
+        if (hits) return shfl_f64(e_out, (int)(grp_base + __ffs(hits) - 1));
+        k += 5u;
+    }
+    for (uint32_t batch = 0; batch < (1u << 20); ++batch) {
+        const uint32_t kk = k + batch * kGroup + gl;
+        const double start = (double)kk * v.dt;
+        const double end = start + v.dt;
+        uint32_t c0 = loc, c1 = kk, c2 = 0, c3 = 0;
+        philox10(c0, c1, c2, c3, v.key0, v.key1);
+        const double e = start + (-log_u53o(((uint64_t)c1 << 32) | c0)) * v.inv_lambda;
+        const bool hit = e < end;
+        const uint32_t hits = (uint32_t)((__ballot(hit) >> grp_base) & 0xFFu);
+        if (gl == 0u) {
+            const uint32_t used = hits ? (uint32_t)__ffs(hits) : kGroup;
+            cnt.philox += used;
+            cnt.draws += used;
         }
         if (hits) return shfl_f64(e, (int)(grp_base + __ffs(hits) - 1));
     }
@@ -1341,7 +1437,7 @@ void fill_config(const nh_config *in, nh_config &c) {
     if (c.block_size == 0) c.block_size = 256;
     if (c.blocks_per_cu == 0) c.blocks_per_cu = 4;
     if (c.rounds_per_graph == 0) c.rounds_per_graph = 8;
-    /* coop_max 0 = default (lanes of one launch / 8); 1 keeps one lane per lineage for every queue > 1 */
+    if (c.table_placement > 1) c.table_placement = 0;
     if (!(c.timeout_s > 0)) c.timeout_s = 600.0;
 }
 
@@ -1672,9 +1768,10 @@ NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, 
     ra.js = d_js;
     ra.ring = d_ring;
     ra.ring_cap = ring_cap;
-    ra.coop_max = cfg.coop_max ? cfg.coop_max : (uint32_t)(((uint64_t)grid * cfg.block_size) / kGroup) + 1;
+    ra.coop_max = cfg.coop_max ? cfg.coop_max : (uint32_t)(((uint64_t)grid * cfg.block_size) / (2 * kGroup)) + 1;
     const nh_scenario *s0 = jobs[0].scenario;
-    const bool lds_table = single && s0->mode == NH_DISPERSAL_SHARED && s0->n_shared <= kLdsTableMax;
+    const bool lds_table =
+        single && cfg.table_placement == 0 && s0->mode == NH_DISPERSAL_SHARED && s0->n_shared <= kLdsTableMax;
     const size_t lds_bytes = lds_table ? sizeof(uint4) * s0->n_shared : 0;
     auto launch_round = [&](hipStream_t s) {
         if (lds_table)
@@ -2173,7 +2270,8 @@ NH_API int nh_server_create(const nh_server_config *config, void *stream, nh_ser
     ra.ring_cap = s->max_jobs;
     ra.lin = s->lin;
     ra.htab = s->d_htab;
-    ra.coop_max = s->cfg.coop_max ? s->cfg.coop_max : (uint32_t)(((uint64_t)s->grid * s->cfg.block_size) / kGroup) + 1;
+    ra.coop_max =
+        s->cfg.coop_max ? s->cfg.coop_max : (uint32_t)(((uint64_t)s->grid * s->cfg.block_size) / (2 * kGroup)) + 1;
     hipStream_t cap_stream;
     if (hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(NH_EDEVICE, "capture stream creation failed"));

@@ -1,0 +1,162 @@
+"""Served form of the Independent algorithm: a request stream through the
+continuous-batching engine (nh_server_* in libnecsim_hip).
+
+Each request is a scenario (landscape, dispersal kernel, nu) and a seed, with
+every individual sampled.  Requests arrive on a Poisson clock; on arrival a
+worker thread builds the scenario's tables (nh_scenario_create), the request is
+submitted to the server, which admits it into the running device batch as soon
+as a contiguous range of resident lineage slots (its HBM footprint) and a job
+slot are free, and the request completes when its last lineage retires.
+Latency = completion (richness on the host) minus arrival.
+
+The plain comparison runs the same requests one at a time, each in its own
+device run (nh_batch_run with one job), in arrival order: a request starts
+when it has arrived and the previous one has finished.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import time
+
+import numpy as np
+
+from . import binding as B
+from . import workloads as W
+
+
+def _build(spec_or_workload):
+    wl = W.materialize(spec_or_workload) if isinstance(spec_or_workload, dict) else spec_or_workload
+    return wl, B.Scenario.from_workload(wl)
+
+
+def _percentiles(lat):
+    a = np.asarray(lat, dtype=np.float64)
+    if len(a) == 0:
+        return {"p50_ms": None, "p99_ms": None, "mean_ms": None, "max_ms": None}
+    return {"p50_ms": float(np.percentile(a, 50) * 1e3), "p99_ms": float(np.percentile(a, 99) * 1e3),
+            "mean_ms": float(a.mean() * 1e3), "max_ms": float(a.max() * 1e3)}
+
+
+def lineage_capacity_for_budget(budget_bytes: int, max_jobs: int) -> int:
+    """Largest resident pool whose device footprint fits the byte budget."""
+    lo, hi = 1, 1 << 30
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if B.server_bytes(mid, max_jobs) <= budget_bytes:
+            lo = mid
+        else:
+            hi = mid
+    return lo
+
+
+# Served jobs share round boundaries, so one round lasts as long as the slowest
+# lineage's events in it; a small cap on each round's horizon advance keeps
+# rounds short for the jobs that just arrived (a long-lived job then takes more,
+# cheap rounds).  The batched form, which only cares about the total, prefers a
+# large cap; the autotuner chooses per workload.
+SERVE_DEFAULTS = {"horizon_step_max": 64.0}
+
+
+def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, lineage_capacity: int | None = None,
+               max_jobs: int = 2048, lookahead: int = 64, config=None, workers: int = 4, timeout_s: float = 900.0):
+    """Serve the stream; returns latency percentiles, throughput and admission statistics."""
+    import torch
+
+    if config is None:
+        config = B.make_config(**SERVE_DEFAULTS)
+    dev = torch.device("cuda:0")
+    if lineage_capacity is None:
+        if hbm_budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info()
+            hbm_budget_bytes = int(0.5 * free)
+        lineage_capacity = lineage_capacity_for_budget(hbm_budget_bytes, max_jobs)
+    stream = torch.cuda.Stream()
+    srv = B.Server(lineage_capacity, max_jobs=max_jobs, lookahead=lookahead, config=config, stream=stream)
+    pool = cf.ThreadPoolExecutor(max_workers=workers)
+    n = len(requests)
+    lat = np.full(n, np.nan)
+    events = individuals = 0
+    building = {}
+    nxt = done = 0
+    peak_pending = peak_active = 0
+    t0 = time.perf_counter()
+    try:
+        while done < n:
+            now = time.perf_counter() - t0
+            if now > timeout_s:
+                raise TimeoutError(f"serving stream did not finish in {timeout_s} s ({done}/{n} done)")
+            while nxt < n and arrivals[nxt] <= now:
+                building[nxt] = pool.submit(_build, requests[nxt])
+                nxt += 1
+            for idx in [k for k, f in building.items() if f.done()]:
+                wl, scn = building.pop(idx).result()
+                with torch.cuda.stream(stream):
+                    N = scn.individuals
+                    samples = torch.arange(N, dtype=torch.int64, device=dev)
+                    out = torch.empty(N, dtype=torch.int64, device=dev)
+                    rich = torch.empty(1, dtype=torch.int64, device=dev)
+                srv.submit(idx, scn, wl.seeds[0], samples, out, rich)
+            active, pending = srv.progress()
+            peak_pending = max(peak_pending, pending + len(building))
+            peak_active = max(peak_active, active)
+            for c in srv.poll():
+                t_done = time.perf_counter() - t0
+                idx = c["tag"]
+                if c["status"] != 0:
+                    raise RuntimeError(f"request {idx} failed with status {c['status']}")
+                lat[idx] = t_done - arrivals[idx]
+                events += c["events"]
+                individuals += c["lineages"]
+                done += 1
+            if not building and nxt < n and srv.progress()[0] == 0:
+                time.sleep(min(0.0005, max(0.0, arrivals[nxt] - (time.perf_counter() - t0))))
+        wall = time.perf_counter() - t0
+    finally:
+        pool.shutdown(wait=True)
+        srv.close()
+    span = wall - float(arrivals[0]) if n else wall
+    third = max(1, n // 3)
+    first, last = np.median(lat[:third]), np.median(lat[-third:])
+    return {"requests": n, "wall_s": wall, "events": int(events), "individuals": int(individuals),
+            "events_per_s": events / span, "individuals_per_s": individuals / span,
+            "offered_requests_per_s": n / float(arrivals[-1] - arrivals[0]) if n > 1 else None,
+            "lineage_capacity": int(lineage_capacity), "max_jobs": max_jobs,
+            "peak_pending": int(peak_pending), "peak_active": int(peak_active),
+            "latency": _percentiles(lat), "latencies_s": lat,
+            # the stream is sustained if requests arriving late wait no longer than early ones
+            "median_latency_first_third_ms": float(first * 1e3), "median_latency_last_third_ms": float(last * 1e3),
+            "sustained": bool(last <= 2.0 * first + 0.05)}
+
+
+def run_plain(arrivals, requests, *, config=None):
+    """The same requests one per device run, in arrival order (each waits for the previous)."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    n = len(requests)
+    lat = np.zeros(n)
+    busy_until = 0.0
+    events = individuals = 0
+    service = 0.0
+    for k, req in enumerate(requests):
+        t_start = time.perf_counter()
+        wl, scn = _build(req)
+        N = scn.individuals
+        samples = torch.arange(N, dtype=torch.int64, device=dev)
+        out = torch.empty(N, dtype=torch.int64, device=dev)
+        rich = torch.empty(1, dtype=torch.int64, device=dev)
+        ws = torch.empty(B.workspace_bytes(N, 1), dtype=torch.uint8, device=dev)
+        st = B.batch_run([(scn, wl.seeds[0], samples, out, rich)], ws, config)[0]
+        torch.cuda.synchronize()
+        dur = time.perf_counter() - t_start
+        scn.close()
+        start = max(float(arrivals[k]), busy_until)
+        busy_until = start + dur
+        lat[k] = busy_until - float(arrivals[k])
+        events += st["events"]
+        individuals += N
+        service += dur
+    span = busy_until - float(arrivals[0])
+    return {"requests": n, "service_s": service, "events": int(events), "individuals": int(individuals),
+            "events_per_s": events / span, "individuals_per_s": individuals / span, "requests_per_s": n / span,
+            "latency": _percentiles(lat), "latencies_s": lat}

@@ -175,13 +175,14 @@ def config4(master_seed: int = 2108, n: int = 256, side_range=(64, 512), nu_rang
 
 def config5_requests(rate: float = 200.0, duration: float = 60.0, seed: int = 5, master_seed: int = 2109,
                      spatial_side=(64, 512), J_range=(1e3, 1e6), nu_range=(1e-6, 1e-2)):
-    """Poisson request stream: arrival times (s) and one workload per request, half C4-like spatial
-    scenarios, half non-spatial demes with J log-uniform in J_range."""
+    """Poisson request stream: arrival times (s) and one request spec per arrival, half config-4-like
+    spatial scenarios, half non-spatial demes with J log-uniform in J_range; materialize() turns a spec
+    into its Workload (done on arrival, so the stream itself stays small)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     n = int(rng.poisson(rate * duration))
     arrivals = np.sort(rng.uniform(0.0, duration, size=n))
     mix = np.random.Generator(np.random.PCG64(master_seed))
-    reqs = []
+    specs = []
     for k in range(n):
         nu = float(math.exp(mix.uniform(math.log(nu_range[0]), math.log(nu_range[1]))))
         seed_k = int(mix.integers(0, 2**62))
@@ -190,8 +191,20 @@ def config5_requests(rate: float = 200.0, duration: float = 60.0, seed: int = 5,
             cap = int(mix.integers(1, 5))
             sigma = float(mix.uniform(1.0, 6.0))
             R = min(int(math.ceil(5.0 * sigma)), (L - 1) // 2)
-            reqs.append(spatial_torus(L, cap, sigma, R, nu, [seed_k], name=f"req{k} spatial L={L}"))
+            specs.append({"kind": "spatial", "L": L, "cap": cap, "sigma": sigma, "R": R, "nu": nu, "seed": seed_k,
+                          "name": f"req{k} spatial L={L}"})
         else:
             J = int(round(math.exp(mix.uniform(math.log(J_range[0]), math.log(J_range[1])))))
-            reqs.append(nonspatial(J, nu, [seed_k], name=f"req{k} nonspatial J={J}"))
-    return arrivals, reqs
+            specs.append({"kind": "nonspatial", "J": J, "nu": nu, "seed": seed_k, "name": f"req{k} nonspatial J={J}"})
+    return arrivals, specs
+
+
+def materialize(spec: dict) -> Workload:
+    if spec["kind"] == "spatial":
+        return spatial_torus(spec["L"], spec["cap"], spec["sigma"], spec["R"], spec["nu"], [spec["seed"]],
+                             name=spec["name"])
+    return nonspatial(spec["J"], spec["nu"], [spec["seed"]], name=spec["name"])
+
+
+def spec_individuals(spec: dict) -> int:
+    return spec["L"] * spec["L"] * spec["cap"] if spec["kind"] == "spatial" else spec["J"]
