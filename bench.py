@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="bound on the oracle baseline's CPU time")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_round_c2_traffic.json"),
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_round_c2_traffic.txt"),
                     help="HBM bytes per round launch from rocprofv3 FETCH_SIZE/WRITE_SIZE runs")
     ap.add_argument("--no-tune", action="store_true", help="use the library defaults instead of autotuning")
     ap.add_argument("--knobs", default=None, help="JSON dict of tuned knobs to use instead of autotuning")
@@ -50,7 +50,29 @@ def parse():
                     help="scenarios of the 256-scenario mix also run one per launch for the comparison")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="length of the served request stream")
     ap.add_argument("--serve-plain", type=int, default=48, help="requests of the stream also run one per launch")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (calibrates rocprofv3 FETCH/WRITE_SIZE)")
     return ap.parse_args()
+
+
+def traffic_from_profile(path: str) -> float | None:
+    """HBM bytes per round launch recorded from rocprofv3 FETCH_SIZE and WRITE_SIZE runs, or None when
+    the kernel source has changed since they were taken."""
+    import hashlib
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2108_05815_amd", "csrc", "necsim_hip.hip")
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    if fields.get("kernel_source_sha256") != digest:
+        return None
+    return float(fields["bytes_per_launch"])
 
 
 def cpu_baseline(wl, budget_s: float) -> dict:
@@ -80,6 +102,14 @@ def main():
               "communication, and multi-GPU runs are not part of this build.", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 30, "copies": 3}))
+        return
     from paper_2108_05815_amd import binding as B
     from paper_2108_05815_amd import roofline as RL
     from paper_2108_05815_amd import workloads as W
@@ -129,11 +159,7 @@ def main():
     round_s = totals["round_kernel_ms"] / 1e3
     achieved = ops / round_s / 1e12 if round_s > 0 else 0.0
     peak = RL.PEAK_LANE_OPS / 1e12
-    traffic = None
-    if os.path.exists(args.traffic):
-        with open(args.traffic) as f:
-            tr = json.load(f)
-        traffic = tr.get("bytes_per_launch")
+    traffic = traffic_from_profile(args.traffic)
     line = {
         "metric": METRIC,
         "value": events_per_s,

@@ -74,8 +74,9 @@ def tune(run, knobs=None, start=None, reps: int = 3, passes: int = 1, log=None):
     best_t = measure(best)
     for _ in range(passes):
         for name, values in knobs.items():
+            measured = best[name]  # the current setting was just measured
             for val in values:
-                if val == best[name]:
+                if val == measured:
                     continue
                 cand = dict(best)
                 cand[name] = val
