@@ -50,6 +50,9 @@ def parse():
                     help="scenarios of the 256-scenario mix also run one per launch for the comparison")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="length of the served request stream")
     ap.add_argument("--serve-plain", type=int, default=48, help="requests of the stream also run one per launch")
+    ap.add_argument("--c3", action="store_true",
+                    help="also run the heterogeneous-habitat workload (1024x1024 fractal map, per-deme tables, "
+                         "10%% sample, nu = 1e-5) and report its gather traffic rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (calibrates rocprofv3 FETCH/WRITE_SIZE)")
     return ap.parse_args()
@@ -198,9 +201,41 @@ def main():
     if not args.no_extras:
         line["batched"] = batched_form(args, B, W, torch)
         line["serve"] = served_form(args, W, torch)
+    if args.c3:
+        line["c3"] = habitat_form(B, W, torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def habitat_form(B, W, torch) -> dict:
+    """The heterogeneous-habitat workload: per-deme alias tables (7.9 GB) gathered from HBM."""
+    from paper_2108_05815_amd import roofline as RL
+    dev = torch.device("cuda:0")
+    wl = W.config3()
+    t0 = time.perf_counter()
+    scn = B.Scenario.from_workload(wl)
+    create_s = time.perf_counter() - t0
+    n = len(wl.samples)
+    s = torch.from_numpy(wl.samples.astype(np.int64)).to(dev)
+    out = torch.empty(n, dtype=torch.int64, device=dev)
+    ws = torch.empty(B.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
+    cfg = B.make_config(event_timing=1)
+    B.batch_run([(scn, 41, s, out, None)], ws, cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = B.batch_run([(scn, wl.seeds[0], s, out, None)], ws, cfg)[0]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # dispersal events each gather a 16-byte alias entry, its row pointer pair (8 B) and the target capacity (4 B)
+    disp = st["events"] - st["speciated"]
+    gather_bytes = disp * RL.BYTES_PER_DISPERSAL_PER_DEME
+    rs = st["round_kernel_ms"] / 1e3
+    return {"workload": wl.name, "lineages": n, "table_gib": scn.table_bytes / 2**30, "create_s": create_s,
+            "seconds": el, "events": st["events"], "events_per_s": st["events"] / el, "individuals_per_s": n / el,
+            "richness": st["richness"], "rounds": st["rounds"],
+            "gather_gb_per_s": gather_bytes / rs / 1e9 if rs > 0 else None,
+            "gather_frac_of_8tbs": gather_bytes / rs / 8e12 if rs > 0 else None}
 
 
 def batched_form(args, B, W, torch) -> dict:

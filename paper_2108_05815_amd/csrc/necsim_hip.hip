@@ -532,55 +532,44 @@ __device__ __forceinline__ double next_event_time_group(const JobView &v, uint32
         const double start = (double)kk * v.dt;
         const double end = start + v.dt;
         const double x0 = quad_bcast<0>(x), x1 = quad_bcast<1>(x), x2 = quad_bcast<2>(x), x3 = quad_bcast<3>(x);
-        bool hit = false;
-        double e_out = 0.0;
-        uint32_t draws_k = 0, philox_k = 0;
-        if (q0) {
-            // interval k, in the one-lane order: leave on e >= end, accept on e > t_last
-            int state = 0; // 0 undecided, 1 hit, 2 left
-            double e = start;
-            const double xs[4] = {x0, x1, x2, x3};
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (state == 0) {
-                    e = e + xs[j];
-                    draws_k = (uint32_t)j + 1u;
-                    if (e >= end) state = 2;
-                    else if (e > t_last) state = 1;
+        // Interval k in the one-lane order (leave on e >= end, accept on e > t_last), branch-free: the
+        // partial sums never decrease, so the first sum that either leaves or passes t_last decides.
+        const double e0 = start + x0, e1 = e0 + x1, e2 = e1 + x2, e3 = e2 + x3;
+        const bool d0 = e0 >= end || e0 > t_last, d1 = e1 >= end || e1 > t_last;
+        const bool d2 = e2 >= end || e2 > t_last, d3 = e3 >= end || e3 > t_last;
+        double e = d0 ? e0 : (d1 ? e1 : (d2 ? e2 : e3));
+        uint32_t draws_k = d0 ? 1u : (d1 ? 2u : (d2 ? 3u : 4u));
+        uint32_t philox_k = (draws_k + 1u) >> 1;
+        bool hit_k = d3 && e < end;
+        if (q0 && !d3) { // rare: four draws neither left interval k nor passed t_last; keep walking
+            uint64_t sec = 0;
+            for (uint32_t j = 4; j < (1u << 24); ++j) {
+                uint64_t r;
+                if ((j & 1u) == 0u) {
+                    uint32_t d0w = loc, d1w = k, d2w = 0, d3w = j >> 1;
+                    philox10(d0w, d1w, d2w, d3w, v.key0, v.key1);
+                    ++philox_k;
+                    r = ((uint64_t)d1w << 32) | d0w;
+                    sec = ((uint64_t)d3w << 32) | d2w;
+                } else {
+                    r = sec;
+                }
+                ++draws_k;
+                e = e + (-log_u53o(r)) * v.inv_lambda;
+                if (e >= end) {
+                    hit_k = false;
+                    break;
+                }
+                if (e > t_last) {
+                    hit_k = true;
+                    break;
                 }
             }
-            philox_k = (draws_k + 1u) >> 1;
-            if (state == 0) { // rare: keep walking interval k from draw 4
-                uint64_t sec = 0;
-                for (uint32_t j = 4; j < (1u << 24); ++j) {
-                    uint64_t r;
-                    if ((j & 1u) == 0u) {
-                        uint32_t d0 = loc, d1 = k, d2 = 0, d3 = j >> 1;
-                        philox10(d0, d1, d2, d3, v.key0, v.key1);
-                        ++philox_k;
-                        r = ((uint64_t)d1 << 32) | d0;
-                        sec = ((uint64_t)d3 << 32) | d2;
-                    } else {
-                        r = sec;
-                    }
-                    ++draws_k;
-                    e = e + (-log_u53o(r)) * v.inv_lambda;
-                    if (e >= end) {
-                        state = 2;
-                        break;
-                    }
-                    if (e > t_last) {
-                        state = 1;
-                        break;
-                    }
-                }
-            }
-            hit = state == 1 && gl == 0u;
-            e_out = e;
-        } else {
-            e_out = start + x;
-            hit = e_out < end;
         }
+        // lanes 4-7: their interval's first draw (start + x) lands before its end, or not
+        const double e_first = start + x;
+        const bool hit = q0 ? (hit_k && gl == 0u) : (e_first < end);
+        const double e_out = q0 ? e : e_first;
         const uint32_t hits = (uint32_t)((__ballot(hit) >> grp_base) & 0xFFu);
         if (gl == 0u) {
             const uint32_t later = hits ? (hits & 1u ? 0u : (uint32_t)(__ffs(hits) - 1) - 3u) : 4u;

@@ -287,3 +287,38 @@ def test_config4_batch_sampled_and_alone_equals_mix(B, torch_mod):
         alone, r, _ = B.simulate(scns[k], wls[k].seeds[0], wls[k].samples)
         assert np.array_equal(alone, outs[k].cpu().numpy().view(np.uint64))
         assert r == got_rich[k]
+
+
+def test_batch_with_empty_and_duplicate_jobs_and_device_entry_point(B, torch_mod):
+    """Empty jobs inside a batch, the same job twice, and nh_simulate_device agree with the plain form."""
+    import ctypes as C
+    torch = torch_mod
+    dev = torch.device("cuda:0")
+    wl = SMALL[2]
+    scn = B.Scenario.from_workload(wl)
+    n = len(wl.samples)
+    s = torch.from_numpy(wl.samples.astype(np.int64)).to(dev)
+    empty = torch.zeros(0, dtype=torch.int64, device=dev)
+    outs = [torch.empty(n, dtype=torch.int64, device=dev) for _ in range(2)]
+    rich = torch.full((4,), -1, dtype=torch.int64, device=dev)
+    jobs = [(scn, 3, empty, torch.zeros(0, dtype=torch.int64, device=dev), rich[0:1]),
+            (scn, 3, s, outs[0], rich[1:2]),
+            (scn, 3, empty, torch.zeros(0, dtype=torch.int64, device=dev), rich[2:3]),
+            (scn, 3, s, outs[1], rich[3:4])]
+    ws = torch.empty(B.workspace_bytes(2 * n, 4), dtype=torch.uint8, device=dev)
+    B.batch_run(jobs, ws)
+    torch.cuda.synchronize()
+    alone, r, _ = B.simulate(scn, 3, wl.samples)
+    assert np.array_equal(outs[0].cpu().numpy().view(np.uint64), alone)
+    assert np.array_equal(outs[1].cpu().numpy().view(np.uint64), alone)
+    assert rich.cpu().tolist() == [0, r, 0, r]
+    # nh_simulate_device: the library allocates its own workspace on the stream
+    out = torch.empty(n, dtype=torch.int64, device=dev)
+    r1 = torch.zeros(1, dtype=torch.int64, device=dev)
+    st = B.nh_stats()
+    rc = B.nh_simulate_device(scn.handle, 3, C.c_void_p(s.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                              C.c_void_p(r1.data_ptr()), None, C.byref(st),
+                              C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), alone) and int(r1.item()) == r
