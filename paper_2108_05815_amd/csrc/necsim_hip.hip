@@ -505,15 +505,30 @@ __device__ __forceinline__ double quad_bcast(double x) {
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// Exchange a 32-bit value between the two quads of each 8-lane half row
+// (lane i <-> lane 7 - i): one DPP move.
+__device__ __forceinline__ uint32_t half_mirror(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141 /* row_half_mirror */, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ double half_mirror_f64(double x) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = half_mirror((uint32_t)b), hi = half_mirror((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // Next event time by a group of 8 lanes, bit-identical to next_event_time().
 // First pass: lanes 0-3 take draws 0-3 of the interval k holding t_last (two
-// Philox blocks, one per lane pair, and four logarithms in one pass), share
-// them by DPP and scan them in order; lanes 4-7 take the first draw of
-// intervals k+1 .. k+4, which start beyond t_last, so that draw alone decides
-// them (an event iff it lands before the interval's end).  The answer is the
-// hit of the lowest interval; interval k keeps walking on its own in the rare
-// case that four draws neither pass t_last nor leave it.  Later passes give
-// one interval to each lane.  Counters record what the one-lane search needs.
+// Philox blocks, one per lane pair, and four logarithms in one pass); lanes
+// 4-7 take the first draw of intervals k+1 .. k+4, which start beyond t_last,
+// so that draw alone decides them (an event iff it lands before the
+// interval's end).  Each quad shares its four draws by DPP and resolves its
+// own part in order -- quad 0 the walk through interval k, quad 1 the lowest
+// of its four intervals with an event -- and the two quads then swap outcomes
+// with one more DPP move; interval k, when it decides, comes first.  Interval
+// k keeps walking on its own in the rare case that four draws neither pass
+// t_last nor leave it.  Later passes give one interval to each lane.
+// Counters record what the one-lane search needs.
 __device__ __forceinline__ double next_event_time_group(const JobView &v, uint32_t loc, double t_last, uint32_t gl,
                                                         uint32_t grp_base, uint32_t *err, Counters &cnt) {
     const double kf = floor(t_last * v.inv_dt);
@@ -529,18 +544,20 @@ __device__ __forceinline__ double next_event_time_group(const JobView &v, uint32
         philox10(c0, c1, c2, c3, v.key0, v.key1);
         const uint64_t first = ((uint64_t)c1 << 32) | c0, second = ((uint64_t)c3 << 32) | c2;
         const double x = (-log_u53o((q0 && (gl & 1u)) ? second : first)) * v.inv_lambda;
-        const double start = (double)kk * v.dt;
-        const double end = start + v.dt;
         const double x0 = quad_bcast<0>(x), x1 = quad_bcast<1>(x), x2 = quad_bcast<2>(x), x3 = quad_bcast<3>(x);
-        // Interval k in the one-lane order (leave on e >= end, accept on e > t_last), branch-free: the
-        // partial sums never decrease, so the first sum that either leaves or passes t_last decides.
-        const double e0 = start + x0, e1 = e0 + x1, e2 = e1 + x2, e3 = e2 + x3;
-        const bool d0 = e0 >= end || e0 > t_last, d1 = e1 >= end || e1 > t_last;
-        const bool d2 = e2 >= end || e2 > t_last, d3 = e3 >= end || e3 > t_last;
+        // Interval starts and ends are exact: dt is a power of two and every index is below 2^31.
+        const double s0 = (double)k * v.dt, s1 = s0 + v.dt, s2 = s1 + v.dt, s3 = s2 + v.dt, s4 = s3 + v.dt,
+                     s5 = s4 + v.dt;
+        // Quad 0, interval k in the one-lane order (leave on e >= end, accept on e > t_last): the partial
+        // sums never decrease, so the first sum that either leaves or passes t_last decides.  Bitwise
+        // operators keep the selection free of branches.
+        const double e0 = s0 + x0, e1 = e0 + x1, e2 = e1 + x2, e3 = e2 + x3;
+        const bool d0 = (e0 >= s1) | (e0 > t_last), d1 = (e1 >= s1) | (e1 > t_last);
+        const bool d2 = (e2 >= s1) | (e2 > t_last), d3 = (e3 >= s1) | (e3 > t_last);
         double e = d0 ? e0 : (d1 ? e1 : (d2 ? e2 : e3));
         uint32_t draws_k = d0 ? 1u : (d1 ? 2u : (d2 ? 3u : 4u));
         uint32_t philox_k = (draws_k + 1u) >> 1;
-        bool hit_k = d3 && e < end;
+        bool hit_k = d3 & (e < s1);
         if (q0 && !d3) { // rare: four draws neither left interval k nor passed t_last; keep walking
             uint64_t sec = 0;
             for (uint32_t j = 4; j < (1u << 24); ++j) {
@@ -556,7 +573,7 @@ __device__ __forceinline__ double next_event_time_group(const JobView &v, uint32
                 }
                 ++draws_k;
                 e = e + (-log_u53o(r)) * v.inv_lambda;
-                if (e >= end) {
+                if (e >= s1) {
                     hit_k = false;
                     break;
                 }
@@ -566,17 +583,25 @@ __device__ __forceinline__ double next_event_time_group(const JobView &v, uint32
                 }
             }
         }
-        // lanes 4-7: their interval's first draw (start + x) lands before its end, or not
-        const double e_first = start + x;
-        const bool hit = q0 ? (hit_k && gl == 0u) : (e_first < end);
-        const double e_out = q0 ? e : e_first;
-        const uint32_t hits = (uint32_t)((__ballot(hit) >> grp_base) & 0xFFu);
+        // Quad 1: the lowest of intervals k+1 .. k+4 whose first draw lands before its end.
+        const double f0 = s1 + x0, f1 = s2 + x1, f2 = s3 + x2, f3 = s4 + x3;
+        const bool g0 = f0 < s2, g1 = f1 < s3, g2 = f2 < s4, g3 = f3 < s5;
+        const double q1_e = g0 ? f0 : (g1 ? f1 : (g2 ? f2 : f3));
+        const uint32_t q1_tag = (uint32_t)(g0 | g1 | g2 | g3) | ((g0 ? 0u : (g1 ? 1u : (g2 ? 2u : 3u))) << 1);
+        // Swap outcomes between the quads; a = interval k's, b = the later intervals'.
+        const double my_e = q0 ? e : q1_e;
+        const uint32_t my_tag = q0 ? (uint32_t)hit_k : q1_tag;
+        const double o_e = half_mirror_f64(my_e);
+        const uint32_t o_tag = half_mirror(my_tag);
+        const uint32_t a_tag = q0 ? my_tag : o_tag, b_tag = q0 ? o_tag : my_tag;
+        const double a_e = q0 ? my_e : o_e, b_e = q0 ? o_e : my_e;
+        const bool a_hit = (a_tag & 1u) != 0u, b_hit = (b_tag & 1u) != 0u;
         if (gl == 0u) {
-            const uint32_t later = hits ? (hits & 1u ? 0u : (uint32_t)(__ffs(hits) - 1) - 3u) : 4u;
+            const uint32_t later = a_hit ? 0u : (b_hit ? (b_tag >> 1) + 1u : 4u);
             cnt.philox += philox_k + later;
             cnt.draws += draws_k + later;
         }
-        if (hits) return shfl_f64(e_out, (int)(grp_base + __ffs(hits) - 1));
+        if (a_hit | b_hit) return a_hit ? a_e : b_e;
         k += 5u;
     }
     for (uint32_t batch = 0; batch < (1u << 20); ++batch) {
@@ -947,18 +972,23 @@ __device__ __forceinline__ void round_one_lane(const RoundArgs &A, uint32_t r, u
 
         bool finish_live = false, finish_dead = false;
         uint64_t sp = 0;
+        // Once the wave has drained its share of the queue there is nothing to pick up, so a lane
+        // stays in the event loop until its lineage leaves the round (no per-event bookkeeping).
+        const bool drained = !q.open && q.chunk_pos >= q.chunk_end;
         if (has) {
             if (t > horizon) {
                 finish_live = true;
             } else {
-                ++ev;
-                if (commit_event<kLds>(v, p, t, sp, cnt)) {
-                    finish_dead = true;
-                } else {
-                    t = next_event_time(v, p.loc, t, err, cnt);
-                    if (t < 0.0) finish_dead = true; // runaway search (flagged)
-                    else if (t > horizon) finish_live = true;
-                }
+                do {
+                    ++ev;
+                    if (commit_event<kLds>(v, p, t, sp, cnt)) {
+                        finish_dead = true;
+                    } else {
+                        t = next_event_time(v, p.loc, t, err, cnt);
+                        if (t < 0.0) finish_dead = true; // runaway search (flagged)
+                        else if (t > horizon) finish_live = true;
+                    }
+                } while (drained && !(finish_dead | finish_live));
             }
         }
         if (finish_dead) {
@@ -1048,18 +1078,23 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
 
         bool finish_live = false, finish_dead = false;
         uint64_t sp = 0;
+        // As in the one-lane layout: a drained wave keeps each group in its event loop.  The 8 lanes
+        // of a group always agree, so they leave the loop together.
+        const bool drained = !q.open && q.chunk_pos >= q.chunk_end;
         if (has) {
             if (t > horizon) {
                 finish_live = true;
             } else {
-                ++ev;
-                if (commit_event_group<kLds>(v, p, t, sp, gl, grp_base, cnt)) {
-                    finish_dead = true;
-                } else {
-                    t = next_event_time_group(v, p.loc, t, gl, grp_base, err, cnt);
-                    if (t < 0.0) finish_dead = true;
-                    else if (t > horizon) finish_live = true;
-                }
+                do {
+                    ++ev;
+                    if (commit_event_group<kLds>(v, p, t, sp, gl, grp_base, cnt)) {
+                        finish_dead = true;
+                    } else {
+                        t = next_event_time_group(v, p.loc, t, gl, grp_base, err, cnt);
+                        if (t < 0.0) finish_dead = true;
+                        else if (t > horizon) finish_live = true;
+                    }
+                } while (drained && !(finish_dead | finish_live));
             }
         }
         if (finish_dead) {
