@@ -175,15 +175,20 @@ __device__ __forceinline__ JobView load_view(const JobDev *__restrict__ J) {
 }
 
 // Philox4x32-10 (Salmon et al. 2011): 10 rounds, two 32x32->64 products per
-// round; the Weyl key bump after the last round is never used.
+// round; the Weyl key bump after the last round is never used.  Each
+// three-way xor is one gfx950 bitop3 instruction (truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ void philox10(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3, uint32_t k0,
                                          uint32_t k1) {
 #pragma unroll
     for (int i = 0; i < 10; ++i) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -341,32 +346,22 @@ __device__ __forceinline__ Pos pos_from_loc(const JobView &v, uint32_t loc) {
     return p;
 }
 
-// The event at (loc, t): draws r0, r1 (call 0) and r2, r3 (call 1) from the
-// event domain keyed on the bits of t.  Speciation iff U(r0) < nu, with the
-// species id from the species domain; otherwise the alias column from r1, the
-// alias coin from r2, the torus offset of the chosen entry, and the deme index
-// from r3.  Returns true on speciation.
-template <bool kLds = false>
-__device__ __forceinline__ bool commit_event(const JobView &v, Pos &p, double t, uint64_t &species, Counters &cnt) {
+// Species id of a lineage that speciates at (loc, t): the species domain of
+// the hash, keyed like the event draws.
+__device__ __forceinline__ uint64_t species_of(const JobView &v, uint32_t loc, double t) {
     const uint64_t tb = (uint64_t)__double_as_longlong(t);
-    const uint32_t tlo = (uint32_t)tb, thi = (uint32_t)(tb >> 32);
-    uint32_t a0 = p.loc, a1 = tlo, a2 = thi, a3 = (1u << 30);
-    philox10(a0, a1, a2, a3, v.key0, v.key1);
-    const uint64_t r0 = ((uint64_t)a1 << 32) | a0;
-    const uint64_t r1 = ((uint64_t)a3 << 32) | a2;
-    cnt.philox += 2;
-    if ((r0 >> 11) < v.nu_thresh) {
-        uint32_t s0 = p.loc, s1 = tlo, s2 = thi, s3 = (2u << 30);
-        philox10(s0, s1, s2, s3, v.key0, v.key1);
-        species = ((uint64_t)s1 << 32) | s0;
-        return true;
-    }
-    uint32_t b0 = p.loc, b1 = tlo, b2 = thi, b3 = (1u << 30) | 1u;
-    philox10(b0, b1, b2, b3, v.key0, v.key1);
-    const uint64_t r2 = ((uint64_t)b1 << 32) | b0;
-    const uint64_t r3 = ((uint64_t)b3 << 32) | b2;
+    uint32_t s0 = loc, s1 = (uint32_t)tb, s2 = (uint32_t)(tb >> 32), s3 = (2u << 30);
+    philox10(s0, s1, s2, s3, v.key0, v.key1);
+    return ((uint64_t)s1 << 32) | s0;
+}
+
+// Dispersal from the event draws: the alias column from r1, the alias coin
+// from r2, the torus offset of the chosen entry, and the deme index from r3.
+// A table staged in LDS is always the shared one.
+template <bool kLds>
+__device__ __forceinline__ void disperse(const JobView &v, Pos &p, uint64_t r1, uint64_t r2, uint64_t r3) {
     uint32_t first, n;
-    if (v.mode == NH_DISPERSAL_SHARED) {
+    if (kLds || v.mode == NH_DISPERSAL_SHARED) {
         first = 0;
         n = v.n_shared;
     } else {
@@ -390,6 +385,27 @@ __device__ __forceinline__ bool commit_event(const JobView &v, Pos &p, double t,
     p.y = (uint32_t)ty;
     p.i = mulhi_index(r3, capt);
     p.loc = target * v.cmax + p.i;
+}
+
+// The event at (loc, t): draws r0, r1 (call 0) and r2, r3 (call 1) from the
+// event domain keyed on the bits of t.  Speciation iff U(r0) < nu (the caller
+// then takes the species id from species_of); otherwise the lineage disperses.
+// Returns true on speciation.
+template <bool kLds = false>
+__device__ __forceinline__ bool commit_event(const JobView &v, Pos &p, double t, Counters &cnt) {
+    const uint64_t tb = (uint64_t)__double_as_longlong(t);
+    const uint32_t tlo = (uint32_t)tb, thi = (uint32_t)(tb >> 32);
+    uint32_t a0 = p.loc, a1 = tlo, a2 = thi, a3 = (1u << 30);
+    philox10(a0, a1, a2, a3, v.key0, v.key1);
+    const uint64_t r0 = ((uint64_t)a1 << 32) | a0;
+    const uint64_t r1 = ((uint64_t)a3 << 32) | a2;
+    cnt.philox += 2;
+    if (__builtin_expect((r0 >> 11) < v.nu_thresh, 0)) return true;
+    uint32_t b0 = p.loc, b1 = tlo, b2 = thi, b3 = (1u << 30) | 1u;
+    philox10(b0, b1, b2, b3, v.key0, v.key1);
+    const uint64_t r2 = ((uint64_t)b1 << 32) | b0;
+    const uint64_t r3 = ((uint64_t)b3 << 32) | b2;
+    disperse<kLds>(v, p, r1, r2, r3);
     return false;
 }
 
@@ -500,15 +516,15 @@ template <int J>
 __device__ __forceinline__ double quad_bcast(double x) {
     constexpr int ctrl = J | (J << 2) | (J << 4) | (J << 6); // quad_perm [J,J,J,J]
     const uint64_t b = (uint64_t)__double_as_longlong(x);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, ctrl, 0xF, 0xF, false);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), ctrl, 0xF, 0xF, false);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, ctrl, 0xF, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), ctrl, 0xF, 0xF, true);
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 // Exchange a 32-bit value between the two quads of each 8-lane half row
 // (lane i <-> lane 7 - i): one DPP move.
 __device__ __forceinline__ uint32_t half_mirror(uint32_t x) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141 /* row_half_mirror */, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x141 /* row_half_mirror */, 0xF, 0xF, true);
 }
 
 __device__ __forceinline__ double half_mirror_f64(double x) {
@@ -532,7 +548,7 @@ __device__ __forceinline__ double half_mirror_f64(double x) {
 __device__ __forceinline__ double next_event_time_group(const JobView &v, uint32_t loc, double t_last, uint32_t gl,
                                                         uint32_t grp_base, uint32_t *err, Counters &cnt) {
     const double kf = floor(t_last * v.inv_dt);
-    if (!(kf < 2147483648.0)) { // every lane runs the one-lane search (same result); lane 0 counts
+    if (__builtin_expect(!(kf < 2147483648.0), 0)) { // every lane runs the one-lane search; lane 0 counts
         Counters dummy;
         return next_event_time_wide(v, loc, t_last, err, gl == 0u ? cnt : dummy);
     }
@@ -558,7 +574,7 @@ __device__ __forceinline__ double next_event_time_group(const JobView &v, uint32
         uint32_t draws_k = d0 ? 1u : (d1 ? 2u : (d2 ? 3u : 4u));
         uint32_t philox_k = (draws_k + 1u) >> 1;
         bool hit_k = d3 & (e < s1);
-        if (q0 && !d3) { // rare: four draws neither left interval k nor passed t_last; keep walking
+        if (__builtin_expect(q0 && !d3, 0)) { // four draws neither left interval k nor passed t_last
             uint64_t sec = 0;
             for (uint32_t j = 4; j < (1u << 24); ++j) {
                 uint64_t r;
@@ -601,7 +617,7 @@ __device__ __forceinline__ double next_event_time_group(const JobView &v, uint32
             cnt.philox += philox_k + later;
             cnt.draws += draws_k + later;
         }
-        if (a_hit | b_hit) return a_hit ? a_e : b_e;
+        if (__builtin_expect(a_hit | b_hit, 1)) return a_hit ? a_e : b_e;
         k += 5u;
     }
     for (uint32_t batch = 0; batch < (1u << 20); ++batch) {
@@ -626,17 +642,15 @@ __device__ __forceinline__ double next_event_time_group(const JobView &v, uint32
 
 // Swap a 32-bit value with the neighbouring lane (lane ^ 1): one DPP move.
 __device__ __forceinline__ uint32_t swap_neighbour(uint32_t x) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1 /* quad_perm [1,0,3,2] */, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1 /* quad_perm [1,0,3,2] */, 0xF, 0xF, true);
 }
 
 // One event for a group: even lanes evaluate event block 0 and odd lanes
 // event block 1 side by side and swap words with their neighbour, so every
-// lane holds r0..r3; the species block is evaluated (by every lane) only when
-// the lineage speciates.  Every lane then applies the same speciation test and
+// lane holds r0..r3.  Every lane then applies the same speciation test and
 // dispersal, so the group stays in agreement without further exchange.
 template <bool kLds = false>
-__device__ __forceinline__ bool commit_event_group(const JobView &v, Pos &p, double t, uint64_t &species,
-                                                   uint32_t gl, uint32_t grp_base, Counters &cnt) {
+__device__ __forceinline__ bool commit_event_group(const JobView &v, Pos &p, double t, uint32_t gl, Counters &cnt) {
     const uint64_t tb = (uint64_t)__double_as_longlong(t);
     const uint32_t tlo = (uint32_t)tb, thi = (uint32_t)(tb >> 32);
     const uint32_t call = gl & 1u;
@@ -649,37 +663,8 @@ __device__ __forceinline__ bool commit_event_group(const JobView &v, Pos &p, dou
     const uint64_t r0 = call ? xa : wa, r1 = call ? xb : wb;
     const uint64_t r2 = call ? wa : xa, r3 = call ? wb : xb;
     if (gl == 0) cnt.philox += 2;
-    if ((r0 >> 11) < v.nu_thresh) {
-        uint32_t s0 = p.loc, s1 = tlo, s2 = thi, s3 = (2u << 30);
-        philox10(s0, s1, s2, s3, v.key0, v.key1);
-        species = ((uint64_t)s1 << 32) | s0;
-        return true;
-    }
-    uint32_t first, n;
-    if (v.mode == NH_DISPERSAL_SHARED) {
-        first = 0;
-        n = v.n_shared;
-    } else {
-        const uint32_t cell = p.y * v.W + p.x;
-        first = v.row_ptr[cell];
-        n = v.row_ptr[cell + 1] - first;
-    }
-    const uint32_t col = mulhi_index(r1, n);
-    const uint4 ent = kLds ? nh_lds_table[first + col] : v.table[first + col];
-    const uint64_t thresh = ((uint64_t)ent.y << 32) | ent.x;
-    const uint32_t off = ((r2 >> 11) < thresh) ? (ent.z & 0xFFFFu) : (ent.z >> 16);
-    int tx = (int)p.x + (int)(off & 0xFFu) - (int)v.R;
-    int ty = (int)p.y + (int)(off >> 8) - (int)v.R;
-    if (tx < 0) tx += (int)v.W;
-    else if (tx >= (int)v.W) tx -= (int)v.W;
-    if (ty < 0) ty += (int)v.H;
-    else if (ty >= (int)v.H) ty -= (int)v.H;
-    const uint32_t target = (uint32_t)ty * v.W + (uint32_t)tx;
-    const uint32_t capt = v.cap_const ? v.cap_const : v.cap[target];
-    p.x = (uint32_t)tx;
-    p.y = (uint32_t)ty;
-    p.i = mulhi_index(r3, capt);
-    p.loc = target * v.cmax + p.i;
+    if (__builtin_expect((r0 >> 11) < v.nu_thresh, 0)) return true;
+    disperse<kLds>(v, p, r1, r2, r3);
     return false;
 }
 
@@ -970,8 +955,7 @@ __device__ __forceinline__ void round_one_lane(const RoundArgs &A, uint32_t r, u
             continue;
         }
 
-        bool finish_live = false, finish_dead = false;
-        uint64_t sp = 0;
+        bool finish_live = false, finish_dead = false, speciated = false;
         // Once the wave has drained its share of the queue there is nothing to pick up, so a lane
         // stays in the event loop until its lineage leaves the round (no per-event bookkeeping).
         const bool drained = !q.open && q.chunk_pos >= q.chunk_end;
@@ -981,8 +965,9 @@ __device__ __forceinline__ void round_one_lane(const RoundArgs &A, uint32_t r, u
             } else {
                 do {
                     ++ev;
-                    if (commit_event<kLds>(v, p, t, sp, cnt)) {
+                    if (commit_event<kLds>(v, p, t, cnt)) {
                         finish_dead = true;
+                        speciated = true;
                     } else {
                         t = next_event_time(v, p.loc, t, err, cnt);
                         if (t < 0.0) finish_dead = true; // runaway search (flagged)
@@ -992,7 +977,7 @@ __device__ __forceinline__ void round_one_lane(const RoundArgs &A, uint32_t r, u
             }
         }
         if (finish_dead) {
-            lin.species[g] = sp;
+            lin.species[g] = speciated ? species_of(v, p.loc, t) : 0ull;
             lin.events[g] += ev;
             has = false;
         }
@@ -1076,8 +1061,7 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
             continue;
         }
 
-        bool finish_live = false, finish_dead = false;
-        uint64_t sp = 0;
+        bool finish_live = false, finish_dead = false, speciated = false;
         // As in the one-lane layout: a drained wave keeps each group in its event loop.  The 8 lanes
         // of a group always agree, so they leave the loop together.
         const bool drained = !q.open && q.chunk_pos >= q.chunk_end;
@@ -1087,8 +1071,9 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
             } else {
                 do {
                     ++ev;
-                    if (commit_event_group<kLds>(v, p, t, sp, gl, grp_base, cnt)) {
+                    if (commit_event_group<kLds>(v, p, t, gl, cnt)) {
                         finish_dead = true;
+                        speciated = true;
                     } else {
                         t = next_event_time_group(v, p.loc, t, gl, grp_base, err, cnt);
                         if (t < 0.0) finish_dead = true;
@@ -1099,7 +1084,7 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
         }
         if (finish_dead) {
             if (leader) {
-                lin.species[g] = sp;
+                lin.species[g] = speciated ? species_of(v, p.loc, t) : 0ull;
                 lin.events[g] += ev;
             }
             has = false;
