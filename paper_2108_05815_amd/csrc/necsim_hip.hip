@@ -668,6 +668,79 @@ __device__ __forceinline__ bool commit_event_group(const JobView &v, Pos &p, dou
     return false;
 }
 
+// One event of a group plus the first pass of the following event-time
+// search, as straight-line code with a single outcome: kStepOk (the lineage
+// dispersed and t is its next event time), kStepSpeciated (p and t are left
+// at the event) or kStepSlow (the lineage dispersed, t is unchanged, and the
+// search must be finished by next_event_time_group: interval k needs more
+// than four draws, no interval of k .. k+4 holds an event, or t is beyond the
+// 32-bit interval range).  Dispersal and the search are evaluated even when
+// the lineage speciates, whose outcome then discards them; every table read
+// stays in bounds either way.  The search is the first pass of
+// next_event_time_group, with the walk flag of quad 0 carried in bit 3 of
+// its tag; counters match what the one-lane path records.
+constexpr uint32_t kStepOk = 0, kStepSpeciated = 1, kStepSlow = 2;
+
+template <bool kLds>
+__device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double &t, uint32_t gl, Counters &cnt) {
+    const uint64_t tb = (uint64_t)__double_as_longlong(t);
+    const uint32_t call = gl & 1u;
+    uint32_t a0 = p.loc, a1 = (uint32_t)tb, a2 = (uint32_t)(tb >> 32), a3 = (1u << 30) | call;
+    philox10(a0, a1, a2, a3, v.key0, v.key1);
+    const uint32_t b0 = swap_neighbour(a0), b1 = swap_neighbour(a1), b2 = swap_neighbour(a2),
+                   b3 = swap_neighbour(a3);
+    const uint64_t wa = ((uint64_t)a1 << 32) | a0, wb = ((uint64_t)a3 << 32) | a2;
+    const uint64_t xa = ((uint64_t)b1 << 32) | b0, xb = ((uint64_t)b3 << 32) | b2;
+    const uint64_t r0 = call ? xa : wa, r1 = call ? xb : wb;
+    const uint64_t r2 = call ? wa : xa, r3 = call ? wb : xb;
+    const bool spec = (r0 >> 11) < v.nu_thresh;
+    Pos q = p;
+    disperse<kLds>(v, q, r1, r2, r3);
+
+    const double kf = floor(t * v.inv_dt);
+    const bool wide = !(kf < 2147483648.0);
+    const uint32_t k = wide ? 0u : (uint32_t)kf;
+    const bool q0 = gl < 4u;
+    const uint32_t kk = q0 ? k : k + (gl - 3u);
+    uint32_t c0 = q.loc, c1 = kk, c2 = 0, c3 = q0 ? (gl >> 1) : 0u;
+    philox10(c0, c1, c2, c3, v.key0, v.key1);
+    const uint64_t first = ((uint64_t)c1 << 32) | c0, second = ((uint64_t)c3 << 32) | c2;
+    const double x = (-log_u53o((q0 && (gl & 1u)) ? second : first)) * v.inv_lambda;
+    const double x0 = quad_bcast<0>(x), x1 = quad_bcast<1>(x), x2 = quad_bcast<2>(x), x3 = quad_bcast<3>(x);
+    const double s0 = (double)k * v.dt, s1 = s0 + v.dt, s2 = s1 + v.dt, s3 = s2 + v.dt, s4 = s3 + v.dt,
+                 s5 = s4 + v.dt;
+    const double e0 = s0 + x0, e1 = e0 + x1, e2 = e1 + x2, e3 = e2 + x3;
+    const bool d0 = (e0 >= s1) | (e0 > t), d1 = (e1 >= s1) | (e1 > t);
+    const bool d2 = (e2 >= s1) | (e2 > t), d3 = (e3 >= s1) | (e3 > t);
+    const double e = d0 ? e0 : (d1 ? e1 : (d2 ? e2 : e3));
+    const uint32_t draws_k = d0 ? 1u : (d1 ? 2u : (d2 ? 3u : 4u));
+    const bool hit_k = d3 & (e < s1);
+    const double f0 = s1 + x0, f1 = s2 + x1, f2 = s3 + x2, f3 = s4 + x3;
+    const bool g0 = f0 < s2, g1 = f1 < s3, g2 = f2 < s4, g3 = f3 < s5;
+    const double q1_e = g0 ? f0 : (g1 ? f1 : (g2 ? f2 : f3));
+    const uint32_t q1_tag = (uint32_t)(g0 | g1 | g2 | g3) | ((g0 ? 0u : (g1 ? 1u : (g2 ? 2u : 3u))) << 1);
+    const double my_e = q0 ? e : q1_e;
+    const uint32_t my_tag = q0 ? ((uint32_t)hit_k | ((uint32_t)!d3 << 3)) : q1_tag;
+    const double o_e = half_mirror_f64(my_e);
+    const uint32_t o_tag = half_mirror(my_tag);
+    const uint32_t a_tag = q0 ? my_tag : o_tag, b_tag = q0 ? o_tag : my_tag;
+    const double a_e = q0 ? my_e : o_e, b_e = q0 ? o_e : my_e;
+    const bool a_hit = (a_tag & 1u) != 0u, b_hit = (b_tag & 1u) != 0u;
+    const bool slow = wide | ((a_tag >> 3) & 1u) | !(a_hit | b_hit);
+
+    const uint32_t later = a_hit ? 0u : (b_hit ? ((b_tag >> 1) & 3u) + 1u : 4u);
+    const bool counted = (gl == 0u) & !spec & !slow;
+    cnt.philox += (gl == 0u ? 2u : 0u) + (counted ? ((draws_k + 1u) >> 1) + later : 0u);
+    cnt.draws += counted ? draws_k + later : 0u;
+
+    p.x = spec ? p.x : q.x;
+    p.y = spec ? p.y : q.y;
+    p.i = spec ? p.i : q.i;
+    p.loc = spec ? p.loc : q.loc;
+    t = (spec | slow) ? t : (a_hit ? a_e : b_e);
+    return spec ? kStepSpeciated : (slow ? kStepSlow : kStepOk);
+}
+
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
@@ -1069,17 +1142,25 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
             if (t > horizon) {
                 finish_live = true;
             } else {
+                // The rare slow search is finished inside the iteration: a group that left the loop
+                // for it would wait there until every other group of the wave had left the loop too.
+                uint32_t st;
                 do {
                     ++ev;
-                    if (commit_event_group<kLds>(v, p, t, gl, cnt)) {
-                        finish_dead = true;
-                        speciated = true;
-                    } else {
+                    st = group_step<kLds>(v, p, t, gl, cnt);
+                    if (__builtin_expect(st == kStepSlow, 0)) {
                         t = next_event_time_group(v, p.loc, t, gl, grp_base, err, cnt);
-                        if (t < 0.0) finish_dead = true;
-                        else if (t > horizon) finish_live = true;
+                        st = t < 0.0 ? kStepSlow : kStepOk; // kStepSlow now marks a runaway search
                     }
-                } while (drained && !(finish_dead | finish_live));
+                } while (drained && st == kStepOk && !(t > horizon));
+                if (st == kStepSpeciated) {
+                    finish_dead = true;
+                    speciated = true;
+                } else if (st == kStepSlow) {
+                    finish_dead = true;
+                } else if (t > horizon) {
+                    finish_live = true;
+                }
             }
         }
         if (finish_dead) {
