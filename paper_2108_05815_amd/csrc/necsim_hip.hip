@@ -395,16 +395,18 @@ template <bool kLds = false>
 __device__ __forceinline__ bool commit_event(const JobView &v, Pos &p, double t, Counters &cnt) {
     const uint64_t tb = (uint64_t)__double_as_longlong(t);
     const uint32_t tlo = (uint32_t)tb, thi = (uint32_t)(tb >> 32);
+    // Both blocks side by side (two independent chains in one lane), block 1
+    // even when the lineage speciates.
     uint32_t a0 = p.loc, a1 = tlo, a2 = thi, a3 = (1u << 30);
+    uint32_t b0 = p.loc, b1 = tlo, b2 = thi, b3 = (1u << 30) | 1u;
     philox10(a0, a1, a2, a3, v.key0, v.key1);
+    philox10(b0, b1, b2, b3, v.key0, v.key1);
     const uint64_t r0 = ((uint64_t)a1 << 32) | a0;
     const uint64_t r1 = ((uint64_t)a3 << 32) | a2;
-    cnt.philox += 2;
-    if (__builtin_expect((r0 >> 11) < v.nu_thresh, 0)) return true;
-    uint32_t b0 = p.loc, b1 = tlo, b2 = thi, b3 = (1u << 30) | 1u;
-    philox10(b0, b1, b2, b3, v.key0, v.key1);
     const uint64_t r2 = ((uint64_t)b1 << 32) | b0;
     const uint64_t r3 = ((uint64_t)b3 << 32) | b2;
+    cnt.philox += 2;
+    if (__builtin_expect((r0 >> 11) < v.nu_thresh, 0)) return true;
     disperse<kLds>(v, p, r1, r2, r3);
     return false;
 }
