@@ -280,13 +280,27 @@ def batched_form(args, B, W, torch) -> dict:
 def served_form(args, W, torch) -> dict:
     """Poisson request stream (200 req/s) through the continuous-batching server, and its first
     requests one per run for comparison."""
+    from paper_2108_05815_amd import binding as B
     from paper_2108_05815_amd import serve as S
     arrivals, specs = W.config5_requests(duration=args.serve_seconds)
     served = S.run_served(arrivals, specs, hbm_budget_bytes=64 << 30)
     m = min(args.serve_plain, len(specs))
     plain = S.run_plain(arrivals[:m], specs[:m])
     prefix = served["latencies_s"][:m]
-    ev_prefix = None
+    # the slowest request again, alone on the idle device: the floor its serial tail sets
+    slow = int(np.nanargmax(served["latencies_s"]))
+    wl, scn = S._build(specs[slow])
+    n = scn.individuals
+    dev = torch.device("cuda:0")
+    s_ids = torch.arange(n, dtype=torch.int64, device=dev)
+    out_ids = torch.empty(n, dtype=torch.int64, device=dev)
+    ws = torch.empty(B.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = B.batch_run([(scn, wl.seeds[0], s_ids, out_ids, None)], ws)[0]
+    torch.cuda.synchronize()
+    alone_s = time.perf_counter() - t0
+    rounds, events, _ = served["per_request"][slow]
     out = {"workload": f"C5: Poisson 200 req/s for {args.serve_seconds:g} s, half spatial (C4-like), half "
                        "non-spatial J 1e3..1e6, all individuals sampled",
            "requests": served["requests"], "p50_ms": served["latency"]["p50_ms"],
@@ -301,8 +315,10 @@ def served_form(args, W, torch) -> dict:
                             "plain_p99_ms": plain["latency"]["p99_ms"],
                             "plain_events_per_s": plain["events_per_s"],
                             "served_p50_ms": float(np.percentile(prefix, 50) * 1e3),
-                            "served_p99_ms": float(np.percentile(prefix, 99) * 1e3)}}
-    del ev_prefix
+                            "served_p99_ms": float(np.percentile(prefix, 99) * 1e3)},
+           "slowest_request": {"spec": {k: v for k, v in specs[slow].items() if k != "name"},
+                               "served_ms": float(served["latencies_s"][slow] * 1e3), "events": events,
+                               "alone_ms": alone_s * 1e3, "alone_events": st["events"]}}
     return out
 
 

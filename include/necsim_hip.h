@@ -99,6 +99,13 @@ typedef struct {
     uint32_t table_placement; /* 0: stage a shared dispersal table in LDS for single-job runs when it
                                  fits (4096 entries); 1: read every table from global memory */
     double timeout_s;     /* wall-clock limit of one run, default 600 */
+    uint32_t solo_max;    /* runs of several jobs (batches, the server): a job whose live lineage count
+                             has fallen to this many or fewer runs its lineages 8 lanes each, at raised
+                             wave priority, on blocks of their own, and advances its horizon by
+                             solo_step per round (its serial tail no longer waits on the horizon
+                             schedule of young jobs); default 0: off */
+    uint32_t reserved;    /* set to zero */
+    double solo_step;     /* horizon advance per round of such a job, default 512 */
 } nh_config;
 
 /* Per-job counters of one run. */

@@ -43,7 +43,8 @@ class nh_config(C.Structure):
     _fields_ = [("horizon0", C.c_double), ("horizon_growth", C.c_double), ("horizon_step_max", C.c_double),
                 ("block_size", C.c_uint32), ("blocks_per_cu", C.c_uint32), ("rounds_per_graph", C.c_uint32),
                 ("event_timing", C.c_uint32), ("coop_max", C.c_uint32), ("table_placement", C.c_uint32),
-                ("timeout_s", C.c_double)]
+                ("timeout_s", C.c_double), ("solo_max", C.c_uint32), ("reserved", C.c_uint32),
+                ("solo_step", C.c_double)]
 
 
 class nh_stats(C.Structure):

@@ -106,6 +106,9 @@ struct JobState {
     unsigned long long events;
     unsigned long long speciated;
     unsigned long long merged;
+    uint32_t solo_round;  // first round of the job's solo schedule (0: not solo)
+    uint32_t solo_pad;
+    double h_base;        // the job's horizon in round solo_round - 1
 };
 
 // Run control block (device memory, inside the workspace).
@@ -113,6 +116,8 @@ struct Ctl {
     uint32_t round;      // round the next round kernel runs
     uint32_t count[3];   // queue length of round r is count[r % 3]
     uint32_t cursor[3];  // work-queue cursor of round r is cursor[r % 3]
+    uint32_t solo[3];    // solo-queue length of round r (multi-job runs), stored from the top of act
+    uint32_t solo_cursor[3];
     uint32_t blocks_done;
     uint32_t error;
     uint32_t n_jobs;
@@ -758,6 +763,8 @@ __global__ void k_setup(Ctl *ctl, JobState *js, const JobDev *jobs, uint32_t n_j
         for (int k = 0; k < 3; ++k) {
             ctl->count[k] = 0;
             ctl->cursor[k] = 0;
+            ctl->solo[k] = 0;
+            ctl->solo_cursor[k] = 0;
         }
         ctl->blocks_done = 0;
         ctl->error = 0;
@@ -776,6 +783,8 @@ __global__ void k_setup(Ctl *ctl, JobState *js, const JobDev *jobs, uint32_t n_j
         js[j].events = 0;
         js[j].speciated = 0;
         js[j].merged = 0;
+        js[j].solo_round = 0;
+        js[j].h_base = 0.0;
     }
 }
 
@@ -799,7 +808,39 @@ struct RoundArgs {
     const double *htab;
     uint32_t coop_max; // queues shorter than this run groups of 8 lanes per lineage
     uint32_t ring_cap;
+    uint32_t n_cap;    // slots of each act array (main queue from the bottom, solo queue from the top)
+    uint32_t solo_max; // multi-job runs: jobs with at most this many live lineages turn solo (0: never)
+    double solo_step;  // horizon advance per round of a solo job
 };
+
+// Horizon of job jb in round r: its schedule by age, or, once the job has
+// turned solo, a fixed advance per round from the horizon it had then.  A
+// job's solo round is set while round solo_round - 1 runs and only read for
+// later rounds, so every lineage of the job sees the same horizon.
+__device__ __forceinline__ double job_horizon(const RoundArgs &A, uint32_t r, uint32_t jb) {
+    const uint32_t sr = A.js[jb].solo_round;
+    if (sr != 0u && r >= sr) return A.js[jb].h_base + (double)(r - sr + 1u) * A.solo_step;
+    return horizon_of(A.htab, r - A.jobs[jb].start_round);
+}
+
+// Where a survivor of round r goes (multi-job runs): a job whose live count
+// has fallen to solo_max or below turns solo from round r + 1 (the first lane
+// to see it records the round and its current horizon) and its survivors go
+// to the solo queue.  Reads of the live count may be stale; that only moves
+// the switch by a round.
+__device__ __forceinline__ bool route_solo(const RoundArgs &A, uint32_t r, uint32_t jb, double horizon) {
+    if (A.solo_max == 0u) return false;
+    JobState &J = A.js[jb];
+    if (__hip_atomic_load(&J.solo_round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return true;
+    if (__hip_atomic_load(&J.remaining, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > A.solo_max) return false;
+    if (atomicCAS(&J.solo_round, 0u, r + 1u) == 0u) J.h_base = horizon;
+    return true;
+}
+
+__device__ __forceinline__ void push_solo(const RoundArgs &A, uint32_t *solo_count, uint32_t *act_out, uint32_t g) {
+    const uint32_t i = atomicAdd(solo_count, 1u);
+    act_out[A.n_cap - 1u - i] = g;
+}
 
 // Retires lineages (speciated, merged, or rejected at init) from their jobs'
 // live counts, one atomic per wave when the retiring lanes share a job.  The
@@ -895,6 +936,8 @@ __global__ void k_job_setup(Ctl *ctl, JobDev *jobs, JobState *js, uint32_t slot)
         js[slot].events = 0;
         js[slot].speciated = 0;
         js[slot].merged = 0;
+        js[slot].solo_round = 0;
+        js[slot].h_base = 0.0;
     }
     for (uint64_t i = tid; i <= (uint64_t)J->rich_mask; i += (uint64_t)gridDim.x * blockDim.x) J->rich_set[i] = ~0ull;
 }
@@ -974,7 +1017,7 @@ __device__ __forceinline__ void wave_push(WaveQueues &q, bool push, uint32_t id,
 
 template <bool kSingleJob, bool kLds>
 __device__ __forceinline__ void round_one_lane(const RoundArgs &A, uint32_t r, uint32_t n_in, Counters &cnt,
-                                               uint32_t *obuf, uint32_t chunk) {
+                                               uint32_t *obuf, uint32_t chunk, bool solo) {
     Ctl *ctl = A.ctl;
     const Lin &lin = A.lin;
     const uint32_t *__restrict__ act_in = lin.act[r & 1];
@@ -985,6 +1028,10 @@ __device__ __forceinline__ void round_one_lane(const RoundArgs &A, uint32_t r, u
     double *__restrict__ t_out = lin.t[(r + 1) & 1];
     uint32_t *err = &ctl->error;
     const uint32_t qin = r % 3, qout = (r + 1) % 3;
+    // the round's input queue: the main queue from the bottom of act_in, or the solo queue from its top
+    uint32_t *cursor = solo ? &ctl->solo_cursor[qin] : &ctl->cursor[qin];
+    const uint32_t pos_base = solo ? A.n_cap - 1u : 0u;
+    const uint32_t pos_sign = solo ? 0xFFFFFFFFu : 1u; // item i sits at pos_base + pos_sign * i
 
     JobView v;
     double w_single = 0.0;
@@ -1002,9 +1049,9 @@ __device__ __forceinline__ void round_one_lane(const RoundArgs &A, uint32_t r, u
         const uint64_t need = __ballot(!has);
         bool retire = false;
         if (need && (q.open || q.chunk_pos < q.chunk_end)) {
-            const uint32_t pos = wave_take(q, need, &ctl->cursor[qin], n_in, chunk);
+            const uint32_t pos = wave_take(q, need, cursor, n_in, chunk);
             if (pos != 0xFFFFFFFFu) {
-                g = act_in[pos];
+                g = act_in[pos_base + pos_sign * pos];
                 if (!kSingleJob) jb = lin.job[g];
                 const uint32_t loc = loc_in[g];
                 t = t_in[g];
@@ -1016,7 +1063,7 @@ __device__ __forceinline__ void round_one_lane(const RoundArgs &A, uint32_t r, u
                 } else {
                     if (!kSingleJob) {
                         v = load_view(&A.jobs[jb]);
-                        horizon = horizon_of(A.htab, r - A.jobs[jb].start_round);
+                        horizon = job_horizon(A, r, jb);
                     }
                     p = pos_from_loc(v, loc);
                     ev = 0;
@@ -1063,14 +1110,16 @@ __device__ __forceinline__ void round_one_lane(const RoundArgs &A, uint32_t r, u
             has = false;
         }
         wave_retire(ctl, A.js, A.ring, A.ring_cap, r, retire || finish_dead, jb);
-        wave_push(q, finish_live, g, obuf, &ctl->count[qout], act_out);
+        const bool to_solo = !kSingleJob && finish_live && route_solo(A, r, jb, horizon);
+        if (to_solo) push_solo(A, &ctl->solo[qout], act_out, g);
+        wave_push(q, finish_live && !to_solo, g, obuf, &ctl->count[qout], act_out);
     }
     wave_flush(q, obuf, &ctl->count[qout], act_out);
 }
 
 template <bool kSingleJob, bool kLds>
 __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint32_t n_in, Counters &cnt,
-                                            uint32_t *obuf, uint32_t chunk) {
+                                            uint32_t *obuf, uint32_t chunk, bool solo) {
     Ctl *ctl = A.ctl;
     const Lin &lin = A.lin;
     const uint32_t *__restrict__ act_in = lin.act[r & 1];
@@ -1081,6 +1130,10 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
     double *__restrict__ t_out = lin.t[(r + 1) & 1];
     uint32_t *err = &ctl->error;
     const uint32_t qin = r % 3, qout = (r + 1) % 3;
+    // the round's input queue: the main queue from the bottom of act_in, or the solo queue from its top
+    uint32_t *cursor = solo ? &ctl->solo_cursor[qin] : &ctl->cursor[qin];
+    const uint32_t pos_base = solo ? A.n_cap - 1u : 0u;
+    const uint32_t pos_sign = solo ? 0xFFFFFFFFu : 1u; // item i sits at pos_base + pos_sign * i
     const uint32_t lane = lane_id(), gl = lane & (kGroup - 1), grp_base = lane & ~(kGroup - 1);
     const bool leader = gl == 0;
 
@@ -1101,10 +1154,10 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
         bool retire = false;     // set on the leader lane of a group whose candidate was merged
         uint32_t retire_jb = 0;
         if (need && (q.open || q.chunk_pos < q.chunk_end)) {
-            const uint32_t pos = wave_take(q, need, &ctl->cursor[qin], n_in, chunk);
+            const uint32_t pos = wave_take(q, need, cursor, n_in, chunk);
             uint32_t take = 0xFFFFFFFFu; // lineage id the group leader took, or none
             if (pos != 0xFFFFFFFFu) {
-                const uint32_t cand = act_in[pos];
+                const uint32_t cand = act_in[pos_base + pos_sign * pos];
                 const uint32_t cjb = kSingleJob ? 0u : lin.job[cand];
                 const uint32_t owner = cull_insert(lin, loc_in, t_in, r, cand, loc_in[cand],
                                                    (uint64_t)__double_as_longlong(t_in[cand]), cjb, err);
@@ -1122,7 +1175,7 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
                 if (!kSingleJob) {
                     jb = lin.job[g];
                     v = load_view(&A.jobs[jb]);
-                    horizon = horizon_of(A.htab, r - A.jobs[jb].start_round);
+                    horizon = job_horizon(A, r, jb);
                 }
                 p = pos_from_loc(v, loc_in[g]);
                 t = t_in[g];
@@ -1183,7 +1236,9 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
         // a group leader retires either the candidate it merged at pickup or its speciated lineage
         const bool dead_leader = finish_dead && leader;
         wave_retire(ctl, A.js, A.ring, A.ring_cap, r, retire || dead_leader, retire ? retire_jb : jb);
-        wave_push(q, finish_live && leader, g, obuf, &ctl->count[qout], act_out);
+        const bool to_solo = !kSingleJob && finish_live && leader && route_solo(A, r, jb, horizon);
+        if (to_solo) push_solo(A, &ctl->solo[qout], act_out, g);
+        wave_push(q, finish_live && leader && !to_solo, g, obuf, &ctl->count[qout], act_out);
     }
     wave_flush(q, obuf, &ctl->count[qout], act_out);
 }
@@ -1191,26 +1246,48 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
 template <bool kSingleJob, bool kLds>
 __global__ __launch_bounds__(256) void k_round(RoundArgs A) {
     const uint32_t r = A.ctl->round;
-    const uint32_t n_in = A.ctl->count[r % 3];
-    if (n_in == 0) return;
-    const bool group = n_in < A.coop_max;
-    const uint64_t lanes_needed = (uint64_t)n_in * (group ? kGroup : 1u);
+    const uint32_t n_main = A.ctl->count[r % 3];
+    const uint32_t n_solo = kSingleJob ? 0u : A.ctl->solo[r % 3];
+    if (n_main == 0 && n_solo == 0) return;
+    __shared__ uint32_t out_stage[kWavesPerBlock][kOutBuf];
+    uint32_t *obuf = out_stage[threadIdx.x / 64];
+    const uint32_t waves_per_block = blockDim.x / 64;
+    Counters cnt;
+    // Multi-job runs: the first blocks take the solo queue, 8 lanes per lineage at raised wave
+    // priority (these are the long serial tails of nearly finished jobs), at most a quarter of the
+    // grid; the other blocks take the main queue.
+    uint32_t solo_blocks = 0;
+    if constexpr (!kSingleJob) {
+        if (n_solo) {
+            const uint64_t need = ((uint64_t)n_solo * kGroup + blockDim.x - 1) / blockDim.x;
+            solo_blocks = (uint32_t)min<uint64_t>(need, gridDim.x / 4); // the host keeps the grid >= 4
+        }
+        if (blockIdx.x < solo_blocks) {
+            __builtin_amdgcn_s_setprio(2);
+            const uint64_t waves = (uint64_t)solo_blocks * waves_per_block;
+            const uint32_t chunk = (uint32_t)min<uint64_t>(32u, n_solo / (4 * waves));
+            round_group<false, false>(A, r, n_solo, cnt, obuf, chunk, true);
+            flush_counters_block(A.ctl, cnt);
+            return;
+        }
+    }
+    if (n_main == 0) return;
+    const uint32_t b = blockIdx.x - solo_blocks, grid = gridDim.x - solo_blocks;
+    const bool group = n_main < A.coop_max;
+    const uint64_t lanes_needed = (uint64_t)n_main * (group ? kGroup : 1u);
     const uint64_t blocks_needed = (lanes_needed + blockDim.x - 1) / blockDim.x;
-    if (blockIdx.x >= blocks_needed) return; // whole workgroup leaves together
+    if (b >= blocks_needed) return; // whole workgroup leaves together
     if (kLds) { // stage the shared dispersal table (single job, shared mode, small table)
         const uint32_t n_tab = A.jobs[0].n_shared;
         const uint4 *__restrict__ src = A.jobs[0].table;
         for (uint32_t i = threadIdx.x; i < n_tab; i += blockDim.x) nh_lds_table[i] = src[i];
         __syncthreads();
     }
-    __shared__ uint32_t out_stage[kWavesPerBlock][kOutBuf];
-    uint32_t *obuf = out_stage[threadIdx.x / 64];
     // fair share of the queue per participating wave (a quarter of it per reservation), capped
-    const uint64_t waves = min((uint64_t)gridDim.x, blocks_needed) * (blockDim.x / 64);
-    const uint32_t chunk = (uint32_t)min<uint64_t>(group ? 32u : 256u, n_in / (4 * waves));
-    Counters cnt;
-    if (group) round_group<kSingleJob, kLds>(A, r, n_in, cnt, obuf, chunk);
-    else round_one_lane<kSingleJob, kLds>(A, r, n_in, cnt, obuf, chunk);
+    const uint64_t waves = min((uint64_t)grid, blocks_needed) * waves_per_block;
+    const uint32_t chunk = (uint32_t)min<uint64_t>(group ? 32u : 256u, n_main / (4 * waves));
+    if (group) round_group<kSingleJob, kLds>(A, r, n_main, cnt, obuf, chunk, false);
+    else round_one_lane<kSingleJob, kLds>(A, r, n_main, cnt, obuf, chunk, false);
     flush_counters_block(A.ctl, cnt);
 }
 
@@ -1220,8 +1297,10 @@ __global__ __launch_bounds__(256) void k_round(RoundArgs A) {
 __global__ void k_advance(Ctl *ctl, unsigned long long *status_host, const uint32_t *ring, uint32_t ring_cap,
                           uint32_t *ring_host) {
     const uint32_t r = ctl->round;
-    const uint32_t n_out = ctl->count[(r + 1) % 3];
+    const uint32_t n_out = ctl->count[(r + 1) % 3] + ctl->solo[(r + 1) % 3];
     ctl->count[(r + 2) % 3] = 0;
+    ctl->solo[(r + 2) % 3] = 0;
+    ctl->solo_cursor[(r + 1) % 3] = 0;
     ctl->cursor[(r + 1) % 3] = 0;
     ctl->round = r + 1;
     if (ring_host) {
@@ -1531,6 +1610,8 @@ void fill_config(const nh_config *in, nh_config &c) {
     if (c.rounds_per_graph == 0) c.rounds_per_graph = 8;
     if (c.table_placement > 1) c.table_placement = 0;
     if (!(c.timeout_s > 0)) c.timeout_s = 600.0;
+    if (!(c.solo_step > 0)) c.solo_step = 512.0;
+    c.reserved = 0;
 }
 
 std::vector<double> horizon_table(const nh_config &c) {
@@ -1861,6 +1942,9 @@ NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, 
     ra.ring = d_ring;
     ra.ring_cap = ring_cap;
     ra.coop_max = cfg.coop_max ? cfg.coop_max : (uint32_t)(((uint64_t)grid * cfg.block_size) / (2 * kGroup)) + 1;
+    ra.n_cap = (uint32_t)n_total;
+    ra.solo_max = (single || grid < 4) ? 0u : cfg.solo_max; // solo blocks never take more than a quarter
+    ra.solo_step = cfg.solo_step;
     const nh_scenario *s0 = jobs[0].scenario;
     const bool lds_table =
         single && cfg.table_placement == 0 && s0->mode == NH_DISPERSAL_SHARED && s0->n_shared <= kLdsTableMax;
@@ -2364,6 +2448,9 @@ NH_API int nh_server_create(const nh_server_config *config, void *stream, nh_ser
     ra.htab = s->d_htab;
     ra.coop_max =
         s->cfg.coop_max ? s->cfg.coop_max : (uint32_t)(((uint64_t)s->grid * s->cfg.block_size) / (2 * kGroup)) + 1;
+    ra.n_cap = (uint32_t)s->cap_lin;
+    ra.solo_max = s->grid < 4 ? 0u : s->cfg.solo_max; // solo blocks never take more than a quarter
+    ra.solo_step = s->cfg.solo_step;
     hipStream_t cap_stream;
     if (hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(NH_EDEVICE, "capture stream creation failed"));

@@ -52,9 +52,12 @@ def lineage_capacity_for_budget(budget_bytes: int, max_jobs: int) -> int:
 # Served jobs share round boundaries, so one round lasts as long as the slowest
 # lineage's events in it; a small cap on each round's horizon advance keeps
 # rounds short for the jobs that just arrived (a long-lived job then takes more,
-# cheap rounds).  The batched form, which only cares about the total, prefers a
-# large cap; the autotuner chooses per workload.
-SERVE_DEFAULTS = {"horizon_step_max": 64.0}
+# cheap rounds).  A job down to its last few lineages (solo_max) leaves that
+# schedule: its lineages run 8 lanes each at raised wave priority and advance
+# solo_step per round, so its serial tail is not paced by young jobs' rounds.
+# The batched form, which only cares about the total, prefers a large cap; the
+# autotuner chooses per workload.
+SERVE_DEFAULTS = {"horizon_step_max": 64.0, "solo_max": 256, "solo_step": 512.0}
 
 
 def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, lineage_capacity: int | None = None,
@@ -75,6 +78,7 @@ def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, linea
     pool = cf.ThreadPoolExecutor(max_workers=workers)
     n = len(requests)
     lat = np.full(n, np.nan)
+    per_request = {}  # request index -> (rounds, events, lineages) from its completion
     events = individuals = 0
     building = {}
     nxt = done = 0
@@ -105,6 +109,7 @@ def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, linea
                 if c["status"] != 0:
                     raise RuntimeError(f"request {idx} failed with status {c['status']}")
                 lat[idx] = t_done - arrivals[idx]
+                per_request[idx] = (int(c["rounds"]), int(c["events"]), int(c["lineages"]))
                 events += c["events"]
                 individuals += c["lineages"]
                 done += 1
@@ -122,7 +127,7 @@ def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, linea
             "offered_requests_per_s": n / float(arrivals[-1] - arrivals[0]) if n > 1 else None,
             "lineage_capacity": int(lineage_capacity), "max_jobs": max_jobs,
             "peak_pending": int(peak_pending), "peak_active": int(peak_active),
-            "latency": _percentiles(lat), "latencies_s": lat,
+            "latency": _percentiles(lat), "latencies_s": lat, "per_request": per_request,
             # the stream is sustained if requests arriving late wait no longer than early ones
             "median_latency_first_third_ms": float(first * 1e3), "median_latency_last_third_ms": float(last * 1e3),
             "sustained": bool(last <= 2.0 * first + 0.05)}

@@ -289,6 +289,36 @@ def test_config4_batch_sampled_and_alone_equals_mix(B, torch_mod):
         assert r == got_rich[k]
 
 
+def test_solo_tails_never_change_results(B, torch_mod):
+    """Routing nearly finished jobs to the solo queue (8 lanes per lineage, own horizon step) is a
+    performance knob only: a batch of mixed scenarios gives the same ids under every setting."""
+    torch = torch_mod
+    dev = torch.device("cuda:0")
+    wls = W.config4()[:24] + [SMALL[k] for k in (0, 2, 4, 5)]
+    for w in wls:
+        if w.samples is None:
+            w.samples = np.arange(int(w.capacity.astype(np.uint64).sum()), dtype=np.uint64)
+    scns = [B.Scenario.from_workload(w) for w in wls]
+    samples = [torch.from_numpy(w.samples.astype(np.int64)).to(dev) for w in wls]
+    n_total = sum(len(w.samples) for w in wls)
+    ws = torch.empty(B.workspace_bytes(n_total, len(wls)), dtype=torch.uint8, device=dev)
+    base = None
+    for cfg in (dict(), dict(solo_max=64), dict(solo_max=4096, solo_step=8.0), dict(solo_max=64, solo_step=1e5),
+                dict(solo_max=1 << 30, solo_step=64.0, coop_max=1)):
+        say("solo setting", cfg, "lineages", n_total)
+        outs = [torch.empty(len(w.samples), dtype=torch.int64, device=dev) for w in wls]
+        rich = torch.zeros(len(wls), dtype=torch.int64, device=dev)
+        jobs = [(scns[k], wls[k].seeds[0], samples[k], outs[k], rich[k:k + 1]) for k in range(len(wls))]
+        st = B.batch_run(jobs, ws, B.make_config(**cfg))
+        got = [o.cpu().numpy() for o in outs] + [rich.cpu().numpy()]
+        assert all(s["speciated"] + s["merged"] == len(w.samples) for s, w in zip(st, wls))
+        if base is None:
+            base = got
+        else:
+            for a, b in zip(got, base):
+                assert np.array_equal(a, b)
+
+
 def test_batch_with_empty_and_duplicate_jobs_and_device_entry_point(B, torch_mod):
     """Empty jobs inside a batch, the same job twice, and nh_simulate_device agree with the plain form."""
     import ctypes as C

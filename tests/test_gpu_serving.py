@@ -38,14 +38,20 @@ def _mix():
     return wl
 
 
-def test_served_results_equal_alone_and_oracle(env):
+SOLO = [None, (256, 64.0), (1 << 30, 8.0)]
+
+
+@pytest.mark.parametrize("solo", SOLO, ids=["default", "solo 256 step 64", "all solo step 8"])
+def test_served_results_equal_alone_and_oracle(env, solo):
     B, torch = env
     dev = torch.device("cuda:0")
     wls = _mix()
     scns = [B.Scenario.from_workload(w) for w in wls]
     biggest = max(len(w.samples) for w in wls)
+    cfg = None if solo is None else B.make_config(solo_max=solo[0], solo_step=solo[1])
+    say("solo setting", solo)
     # a pool that holds the biggest job but not everything at once: admissions must wait
-    srv = B.Server(lineage_capacity=biggest + 3000, max_jobs=8, lookahead=4)
+    srv = B.Server(lineage_capacity=biggest + 3000, max_jobs=8, lookahead=4, config=cfg)
     outs, submitted = {}, 0
     order = list(range(len(wls)))
     done = {}
