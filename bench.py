@@ -198,6 +198,16 @@ def main():
             "draws_per_event": totals["exp_draws"] / max(1, totals["events"]),
         },
     }
+    # the host-buffer entry point (nh_simulate): the same runs with samples uploaded and species
+    # downloaded over PCIe each time; context only, never the value
+    t0 = time.perf_counter()
+    host_ev = 0
+    for k in range(5):
+        _, _, st_h = B.simulate(scn, 42 + k, wl.samples)
+        host_ev += st_h["events"]
+    host_s = time.perf_counter() - t0
+    line["host_buffers"] = {"entry": "nh_simulate", "runs": 5, "ms_per_run": host_s * 200.0,
+                            "events_per_s": host_ev / host_s}
     if not args.no_extras:
         line["batched"] = batched_form(args, B, W, torch)
         line["serve"] = served_form(args, W, torch)
@@ -209,7 +219,7 @@ def main():
 
 
 def habitat_form(B, W, torch) -> dict:
-    """The heterogeneous-habitat workload: per-deme alias tables (7.9 GB) gathered from HBM."""
+    """The heterogeneous-habitat workload: per-deme alias tables (about 10 GiB) gathered from HBM."""
     from paper_2108_05815_amd import roofline as RL
     dev = torch.device("cuda:0")
     wl = W.config3()
