@@ -93,7 +93,8 @@ struct JobDev {
     uint64_t n_individuals;
     uint32_t W, H, cmax, R;
     uint32_t mode, n_shared, cap_const, rich_mask;
-    uint32_t lin_base, n, start_round, pad;
+    uint32_t lin_base, n, start_round;
+    uint32_t caps_in_table; // per-deme entries hold both targets' capacities (every capacity < 2^16)
 };
 
 // Per-job counters, written by the kernels.
@@ -150,7 +151,7 @@ struct JobView {
     const uint4 *table;
     const uint32_t *row_ptr;
     const uint32_t *cap;
-    uint32_t W, H, cmax, R, mode, n_shared, cap_const;
+    uint32_t W, H, cmax, R, mode, n_shared, cap_const, caps_in_table;
 };
 
 // Op counters of one lane (summed per wave at the end of a kernel).
@@ -176,6 +177,7 @@ __device__ __forceinline__ JobView load_view(const JobDev *__restrict__ J) {
     v.mode = J->mode;
     v.n_shared = J->n_shared;
     v.cap_const = J->cap_const;
+    v.caps_in_table = J->caps_in_table;
     return v;
 }
 
@@ -377,7 +379,8 @@ __device__ __forceinline__ void disperse(const JobView &v, Pos &p, uint64_t r1, 
     const uint32_t col = mulhi_index(r1, n);
     const uint4 ent = kLds ? nh_lds_table[first + col] : v.table[first + col];
     const uint64_t thresh = ((uint64_t)ent.y << 32) | ent.x;
-    const uint32_t off = ((r2 >> 11) < thresh) ? (ent.z & 0xFFFFu) : (ent.z >> 16);
+    const bool primary = (r2 >> 11) < thresh;
+    const uint32_t off = primary ? (ent.z & 0xFFFFu) : (ent.z >> 16);
     int tx = (int)p.x + (int)(off & 0xFFu) - (int)v.R;
     int ty = (int)p.y + (int)(off >> 8) - (int)v.R;
     if (tx < 0) tx += (int)v.W;
@@ -385,7 +388,9 @@ __device__ __forceinline__ void disperse(const JobView &v, Pos &p, uint64_t r1, 
     if (ty < 0) ty += (int)v.H;
     else if (ty >= (int)v.H) ty -= (int)v.H;
     const uint32_t target = (uint32_t)ty * v.W + (uint32_t)tx;
-    const uint32_t capt = v.cap_const ? v.cap_const : v.cap[target];
+    const uint32_t capt = v.cap_const       ? v.cap_const
+                          : v.caps_in_table ? (primary ? (ent.w & 0xFFFFu) : (ent.w >> 16))
+                                            : v.cap[target];
     p.x = (uint32_t)tx;
     p.y = (uint32_t)ty;
     p.i = mulhi_index(r3, capt);
@@ -1456,6 +1461,13 @@ struct TableBuilder {
             if (mass(cell, k) > 0.0) ++n;
         return n;
     }
+    uint32_t target_cap(int64_t cell, uint32_t k) const {
+        const int64_t x = cell % W, y = cell / W;
+        const int64_t dx = (int64_t)(k % side) - R, dy = (int64_t)(k / side) - R;
+        const int64_t tx = ((x + dx) % (int64_t)W + W) % W;
+        const int64_t ty = ((y + dy) % (int64_t)H + H) % H;
+        return cap[ty * W + tx];
+    }
     double mass(int64_t cell, uint32_t k) const {
         double wk = weights[k];
         if (cell >= 0) {
@@ -1482,9 +1494,13 @@ struct TableBuilder {
         alias.resize(n);
         vose(w.data(), n, prob.data(), alias.data(), p, small, large);
         auto pack = [&](uint32_t k) { return (k % side) | ((k / side) << 8); };
+        // Per-deme tables also carry both candidate targets' capacities (16 bits each, 0 when one
+        // does not fit), so dispersal needs no further dependent load for the deme index.
+        auto cap16 = [&](uint32_t k) { const uint32_t c = target_cap(cell, k); return c <= 0xFFFFu ? c : 0u; };
         for (uint32_t c = 0; c < n; ++c) {
             const uint64_t th = u53_threshold(prob[c]);
-            out[c] = make_uint4((uint32_t)th, (uint32_t)(th >> 32), pack(kidx[c]) | (pack(kidx[alias[c]]) << 16), 0u);
+            const uint32_t caps = cell >= 0 ? (cap16(kidx[c]) | (cap16(kidx[alias[c]]) << 16)) : 0u;
+            out[c] = make_uint4((uint32_t)th, (uint32_t)(th >> 32), pack(kidx[c]) | (pack(kidx[alias[c]]) << 16), caps);
         }
         return n;
     }
@@ -1886,6 +1902,7 @@ NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, 
         d.mode = s->mode;
         d.n_shared = s->n_shared;
         d.cap_const = s->cap_const;
+        d.caps_in_table = (s->mode == NH_DISPERSAL_PER_DEME && s->cmax <= 0xFFFFu) ? 1u : 0u;
         d.lin_base = (uint32_t)base;
         d.n = (uint32_t)jobs[j].n;
         d.start_round = 0;
@@ -2282,6 +2299,7 @@ void job_descriptor(JobDev &d, const nh_job &job, unsigned long long *rich_set, 
     d.mode = sc->mode;
     d.n_shared = sc->n_shared;
     d.cap_const = sc->cap_const;
+    d.caps_in_table = (sc->mode == NH_DISPERSAL_PER_DEME && sc->cmax <= 0xFFFFu) ? 1u : 0u;
     d.lin_base = (uint32_t)lin_base;
     d.n = (uint32_t)job.n;
     d.start_round = 0;
