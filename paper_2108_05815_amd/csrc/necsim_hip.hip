@@ -222,6 +222,15 @@ __device__ __forceinline__ uint32_t mulhi_index(uint64_t r, uint32_t n) {
 // split into a 32-bit head and a tail.  Every floating-point operation is
 // spelled out (no contraction), so the result is the same bits on any
 // IEEE-754 binary64 machine that evaluates the same sequence.
+// IEEE fused multiply-add d = a*b + c in the three-address encoding: with the
+// two-address form the compiler copies each loop-invariant coefficient into the
+// accumulator first (one extra move per Horner step).
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 __device__ __forceinline__ double log_u53o(uint64_t r) {
     const uint64_t q = (r >> 11) + 1ull;          // 1 .. 2^53
     const int nb = 64 - __clzll((long long)q);     // bit length, 1 .. 54
@@ -239,15 +248,15 @@ __device__ __forceinline__ double log_u53o(uint64_t r) {
     const double s = f / (2.0 + f);
     const double z = s * s;
     double p = 1.0 / 21.0;
-    p = __builtin_fma(p, z, 1.0 / 19.0);
-    p = __builtin_fma(p, z, 1.0 / 17.0);
-    p = __builtin_fma(p, z, 1.0 / 15.0);
-    p = __builtin_fma(p, z, 1.0 / 13.0);
-    p = __builtin_fma(p, z, 1.0 / 11.0);
-    p = __builtin_fma(p, z, 1.0 / 9.0);
-    p = __builtin_fma(p, z, 1.0 / 7.0);
-    p = __builtin_fma(p, z, 1.0 / 5.0);
-    p = __builtin_fma(p, z, 1.0 / 3.0);
+    p = fma3(p, z, 1.0 / 19.0);
+    p = fma3(p, z, 1.0 / 17.0);
+    p = fma3(p, z, 1.0 / 15.0);
+    p = fma3(p, z, 1.0 / 13.0);
+    p = fma3(p, z, 1.0 / 11.0);
+    p = fma3(p, z, 1.0 / 9.0);
+    p = fma3(p, z, 1.0 / 7.0);
+    p = fma3(p, z, 1.0 / 5.0);
+    p = fma3(p, z, 1.0 / 3.0);
     p = p * z;
     const double two_s = s + s;
     const double log_m = __builtin_fma(two_s, p, two_s);
@@ -381,18 +390,17 @@ __device__ __forceinline__ void disperse(const JobView &v, Pos &p, uint64_t r1, 
     const uint64_t thresh = ((uint64_t)ent.y << 32) | ent.x;
     const bool primary = (r2 >> 11) < thresh;
     const uint32_t off = primary ? (ent.z & 0xFFFFu) : (ent.z >> 16);
-    int tx = (int)p.x + (int)(off & 0xFFu) - (int)v.R;
-    int ty = (int)p.y + (int)(off >> 8) - (int)v.R;
-    if (tx < 0) tx += (int)v.W;
-    else if (tx >= (int)v.W) tx -= (int)v.W;
-    if (ty < 0) ty += (int)v.H;
-    else if (ty >= (int)v.H) ty -= (int)v.H;
-    const uint32_t target = (uint32_t)ty * v.W + (uint32_t)tx;
+    // Torus wrap without compares: a = x + dx + W lies in [W - R, 2W + R) because 2R + 1 <= W,
+    // and of a, a - W, a - 2W (unsigned, so the ones below zero are huge) the smallest is a mod W.
+    const uint32_t ax = p.x + (off & 0xFFu) + (v.W - v.R), ay = p.y + (off >> 8) + (v.H - v.R);
+    const uint32_t tx = min(ax, min(ax - v.W, ax - 2u * v.W));
+    const uint32_t ty = min(ay, min(ay - v.H, ay - 2u * v.H));
+    const uint32_t target = ty * v.W + tx;
     const uint32_t capt = v.cap_const       ? v.cap_const
                           : v.caps_in_table ? (primary ? (ent.w & 0xFFFFu) : (ent.w >> 16))
                                             : v.cap[target];
-    p.x = (uint32_t)tx;
-    p.y = (uint32_t)ty;
+    p.x = tx;
+    p.y = ty;
     p.i = mulhi_index(r3, capt);
     p.loc = target * v.cmax + p.i;
 }
@@ -719,7 +727,7 @@ __device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double 
     const uint64_t first = ((uint64_t)c1 << 32) | c0, second = ((uint64_t)c3 << 32) | c2;
     const double x = (-log_u53o((q0 && (gl & 1u)) ? second : first)) * v.inv_lambda;
     const double x0 = quad_bcast<0>(x), x1 = quad_bcast<1>(x), x2 = quad_bcast<2>(x), x3 = quad_bcast<3>(x);
-    const double s0 = (double)k * v.dt, s1 = s0 + v.dt, s2 = s1 + v.dt, s3 = s2 + v.dt, s4 = s3 + v.dt,
+    const double s0 = kf * v.dt, s1 = s0 + v.dt, s2 = s1 + v.dt, s3 = s2 + v.dt, s4 = s3 + v.dt,
                  s5 = s4 + v.dt;
     const double e0 = s0 + x0, e1 = e0 + x1, e2 = e1 + x2, e3 = e2 + x3;
     const bool d0 = (e0 >= s1) | (e0 > t), d1 = (e1 >= s1) | (e1 > t);
