@@ -49,6 +49,8 @@ extern "C" {
 #define NH_ENOMEM (-2)   /* host or device allocation failed, or workspace too small */
 #define NH_EDEVICE (-3)  /* HIP runtime error or kernel-reported failure */
 #define NH_ETIMEOUT (-4) /* the run exceeded nh_config.timeout_s */
+#define NH_SUSPENDED 1   /* not an error: the run stopped at nh_config.max_rounds with its state in the
+                            workspace; nh_batch_resume continues it */
 
 #define NH_DISPERSAL_SHARED 0u   /* one alias table over the kernel, shared by every deme */
 #define NH_DISPERSAL_PER_DEME 1u /* one table per habitable deme over weight x target capacity */
@@ -106,6 +108,10 @@ typedef struct {
                              schedule of young jobs); default 0: off */
     uint32_t reserved;    /* set to zero */
     double solo_step;     /* horizon advance per round of such a job, default 512 */
+    uint32_t max_rounds;  /* nh_batch_run / nh_batch_resume: stop after at least this many rounds of the
+                             call (at the first launch boundary past it) and return NH_SUSPENDED with
+                             the run's whole state in the workspace; default 0: run to the end */
+    uint32_t reserved2;   /* set to zero */
 } nh_config;
 
 /* Per-job counters of one run. */
@@ -174,6 +180,23 @@ uint64_t nh_scenario_footprint_bytes(const nh_scenario *scenario, uint64_t n_sam
  * small; NH_EDEVICE on a HIP error; NH_ETIMEOUT if cfg->timeout_s passes. */
 int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint64_t workspace_bytes,
                  const nh_config *cfg, nh_stats *stats, void *stream);
+
+/* Continues a run that nh_batch_run (or an earlier resume) left suspended
+ * (NH_SUSPENDED). Between rounds the workspace is a complete checkpoint: every
+ * future draw depends only on (seed, location, time) (chapter "The Declaration of
+ * Independence", priming), and the workspace holds each lineage's location and
+ * next event time, the merge links, the cull table and the per-job counters; the
+ * device addresses it also holds (job descriptors) are written again by the
+ * resume. So the caller may copy the workspace bytes to the host, free or reuse
+ * the device memory, and later copy them back into any 256-byte-aligned buffer of
+ * the same size; the results are bitwise those of an uninterrupted run. Bytes
+ * that are not such a copy give undefined results. jobs must be the same list
+ * (same order, scenarios, seeds, sizes and sample ids; the output buffers may
+ * move). cfg may differ (tuning knobs never change results); cfg->max_rounds may
+ * suspend again. Returns as nh_batch_run; stats count the events of the whole run
+ * so far and rounds since its start. */
+int nh_batch_resume(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint64_t workspace_bytes,
+                    const nh_config *cfg, nh_stats *stats, void *stream);
 
 /* One job with device buffers; allocates its own workspace (hipMallocAsync on
  * the stream).  Same semantics as nh_batch_run with one job. */

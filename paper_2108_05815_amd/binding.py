@@ -24,6 +24,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 NH_OK, NH_EINVAL, NH_ENOMEM, NH_EDEVICE, NH_ETIMEOUT = 0, -1, -2, -3, -4
+NH_SUSPENDED = 1
 NH_DISPERSAL_SHARED, NH_DISPERSAL_PER_DEME = 0, 1
 
 
@@ -44,7 +45,7 @@ class nh_config(C.Structure):
                 ("block_size", C.c_uint32), ("blocks_per_cu", C.c_uint32), ("rounds_per_graph", C.c_uint32),
                 ("event_timing", C.c_uint32), ("coop_max", C.c_uint32), ("table_placement", C.c_uint32),
                 ("timeout_s", C.c_double), ("solo_max", C.c_uint32), ("reserved", C.c_uint32),
-                ("solo_step", C.c_double)]
+                ("solo_step", C.c_double), ("max_rounds", C.c_uint32), ("reserved2", C.c_uint32)]
 
 
 class nh_stats(C.Structure):
@@ -91,6 +92,8 @@ _lib.nh_scenario_footprint_bytes.restype = C.c_uint64
 _lib.nh_batch_run.argtypes = [C.POINTER(nh_job), C.c_uint32, C.c_void_p, C.c_uint64, C.POINTER(nh_config),
                               C.POINTER(nh_stats), C.c_void_p]
 _lib.nh_batch_run.restype = C.c_int
+_lib.nh_batch_resume.argtypes = _lib.nh_batch_run.argtypes
+_lib.nh_batch_resume.restype = C.c_int
 _lib.nh_simulate_device.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
                                     C.POINTER(nh_config), C.POINTER(nh_stats), C.c_void_p]
 _lib.nh_simulate_device.restype = C.c_int
@@ -124,6 +127,7 @@ nh_scenario_table_bytes = _lib.nh_scenario_table_bytes
 nh_workspace_bytes = _lib.nh_workspace_bytes
 nh_scenario_footprint_bytes = _lib.nh_scenario_footprint_bytes
 nh_batch_run = _lib.nh_batch_run
+nh_batch_resume = _lib.nh_batch_resume
 nh_simulate_device = _lib.nh_simulate_device
 nh_simulate = _lib.nh_simulate
 nh_last_error = _lib.nh_last_error
@@ -137,7 +141,8 @@ nh_server_drain = _lib.nh_server_drain
 nh_server_destroy = _lib.nh_server_destroy
 
 EXPORTED = ["nh_scenario_create", "nh_scenario_destroy", "nh_scenario_individuals", "nh_scenario_table_bytes",
-            "nh_workspace_bytes", "nh_scenario_footprint_bytes", "nh_batch_run", "nh_simulate_device",
+            "nh_workspace_bytes", "nh_scenario_footprint_bytes", "nh_batch_run", "nh_batch_resume",
+            "nh_simulate_device",
             "nh_simulate", "nh_last_error", "nh_version", "nh_server_bytes", "nh_server_create",
             "nh_server_submit", "nh_server_progress", "nh_server_poll", "nh_server_drain", "nh_server_destroy"]
 
@@ -299,13 +304,7 @@ class Server:
             pass
 
 
-def batch_run(jobs, workspace, config: nh_config | None = None, stream=None):
-    """nh_batch_run over device buffers.
-
-    jobs: list of (Scenario, seed, samples_tensor u64/int64 on the device, species_out tensor,
-    richness_out tensor or None).  workspace: a uint8 device tensor of at least
-    workspace_bytes(sum n, len(jobs)) bytes.  stream: a torch.cuda.Stream or None (current stream).
-    Returns the list of per-job stats dicts."""
+def _batch(fn, name, jobs, workspace, config, stream):
     import torch
 
     arr = (nh_job * len(jobs))()
@@ -313,7 +312,24 @@ def batch_run(jobs, workspace, config: nh_config | None = None, stream=None):
         arr[k] = _job(scn, seed, samples, out, rich)
     st = (nh_stats * len(jobs))()
     s = stream if stream is not None else torch.cuda.current_stream()
-    _check(_lib.nh_batch_run(arr, len(jobs), workspace.data_ptr(), workspace.numel(),
-                             C.byref(config) if config is not None else None, st, C.c_void_p(s.cuda_stream)),
-           "nh_batch_run")
-    return [x.as_dict() for x in st]
+    rc = fn(arr, len(jobs), workspace.data_ptr(), workspace.numel(), C.byref(config) if config is not None else None,
+            st, C.c_void_p(s.cuda_stream))
+    if rc != NH_SUSPENDED:
+        _check(rc, name)
+    return [dict(x.as_dict(), suspended=rc == NH_SUSPENDED) for x in st]
+
+
+def batch_run(jobs, workspace, config: nh_config | None = None, stream=None):
+    """nh_batch_run over device buffers.
+
+    jobs: list of (Scenario, seed, samples_tensor u64/int64 on the device, species_out tensor,
+    richness_out tensor or None).  workspace: a uint8 device tensor of at least
+    workspace_bytes(sum n, len(jobs)) bytes.  stream: a torch.cuda.Stream or None (current stream).
+    Returns the list of per-job stats dicts; each has suspended=True if config.max_rounds stopped
+    the run (continue it with batch_resume)."""
+    return _batch(_lib.nh_batch_run, "nh_batch_run", jobs, workspace, config, stream)
+
+
+def batch_resume(jobs, workspace, config: nh_config | None = None, stream=None):
+    """nh_batch_resume: continue a suspended run from the state in `workspace` (the same jobs)."""
+    return _batch(_lib.nh_batch_resume, "nh_batch_resume", jobs, workspace, config, stream)

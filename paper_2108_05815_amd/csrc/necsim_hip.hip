@@ -1830,8 +1830,12 @@ NH_API uint64_t nh_scenario_footprint_bytes(const nh_scenario *s, uint64_t n_sam
     return (s ? s->table_bytes : 0) + layout(n_samples, 1).total;
 }
 
-NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint64_t workspace_bytes,
-                        const nh_config *cfg_in, nh_stats *stats, void *stream_ptr) {
+namespace {
+
+// One device run over many jobs, from the start or (resume) from the state a
+// suspended run left in the workspace.
+int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint64_t workspace_bytes,
+                   const nh_config *cfg_in, nh_stats *stats, void *stream_ptr, bool resume) {
     using clock = std::chrono::steady_clock;
     hipStream_t stream = (hipStream_t)stream_ptr;
     if (n_jobs == 0) return NH_OK;
@@ -1938,17 +1942,30 @@ NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, 
     int n_cu = 0;
     HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
 
+    // The first round this call runs: 1 for a new run; for a resume, the round
+    // the suspended run would have run next (its control block says which).
+    uint32_t base_round = 1;
+    if (resume) {
+        Ctl c0;
+        HIP_TRY(hipMemcpyAsync(&c0, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        if (c0.n_jobs != n_jobs || c0.round == 0)
+            return fail(NH_EINVAL, "the workspace does not hold a suspended run of these %u jobs", n_jobs);
+        base_round = c0.round;
+    }
     HIP_TRY(hipEventRecord(ev0, stream));
     HIP_TRY(hipMemcpyAsync(d_jobs, hj.data(), sizeof(JobDev) * n_jobs, hipMemcpyHostToDevice, stream));
     HIP_TRY(hipMemcpyAsync(d_htab, htab.data(), sizeof(double) * kMaxHorizons, hipMemcpyHostToDevice, stream));
-    const uint32_t first_round = 1;
-    k_setup<<<std::max<uint32_t>(1, (n_jobs + 255) / 256), 256, 0, stream>>>(ctl, d_js, d_jobs, n_jobs, first_round);
-    k_fill_u64<<<1024, 256, 0, stream>>>(lin.hash, L.hcap, 0ull);
-    if (rich_off) k_fill_u64<<<1024, 256, 0, stream>>>(rich, rich_off, ~0ull);
-    if (n_total) {
-        const uint32_t blocks = (uint32_t)((n_total + 255) / 256);
-        k_init<<<blocks, 256, 0, stream>>>(ctl, d_jobs, n_jobs, -1, d_js, d_ring, ring_cap, lin, 0,
-                                           (uint32_t)n_total);
+    if (!resume) {
+        k_setup<<<std::max<uint32_t>(1, (n_jobs + 255) / 256), 256, 0, stream>>>(ctl, d_js, d_jobs, n_jobs,
+                                                                                 base_round);
+        k_fill_u64<<<1024, 256, 0, stream>>>(lin.hash, L.hcap, 0ull);
+        if (rich_off) k_fill_u64<<<1024, 256, 0, stream>>>(rich, rich_off, ~0ull);
+        if (n_total) {
+            const uint32_t blocks = (uint32_t)((n_total + 255) / 256);
+            k_init<<<blocks, 256, 0, stream>>>(ctl, d_jobs, n_jobs, -1, d_js, d_ring, ring_cap, lin, 0,
+                                               (uint32_t)n_total);
+        }
     }
     HIP_TRY(hipGetLastError());
     // The status word: round 0 and "not finished" until the first round kernel reports.
@@ -2059,9 +2076,11 @@ NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, 
         return NH_OK;
     };
     const auto t_start = clock::now();
-    uint32_t final_round = 0;
+    uint32_t final_round = base_round - 1;
+    bool suspended = false;
     if (n_total) {
-        // Keep two launches in flight; stop when a round reports an empty queue.
+        // Keep two launches in flight; stop when a round reports an empty queue, or, past
+        // cfg.max_rounds, once every enqueued round has run.
         if (int rc = enqueue()) return rc;
         if (int rc = enqueue()) return rc;
         uint64_t spins = 0;
@@ -2070,12 +2089,18 @@ NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, 
             const uint32_t next_round = (uint32_t)(word >> 32);
             const uint32_t live = (uint32_t)(word & 0x7FFFFFFFu);
             const bool errflag = (word >> 31) & 1u;
-            if (next_round >= 2 && (live == 0 || errflag)) {
+            const uint64_t completed = next_round > base_round ? next_round - base_round : 0;
+            if (completed > 0 && (live == 0 || errflag)) {
                 final_round = next_round - 1;
                 break;
             }
-            const uint64_t completed = next_round >= 1 ? next_round - 1 : 0;
-            if (rounds_enqueued < completed + 2 * per_launch) {
+            const bool capped = cfg.max_rounds != 0 && rounds_enqueued >= cfg.max_rounds;
+            if (capped && completed >= rounds_enqueued) {
+                final_round = next_round - 1;
+                suspended = true;
+                break;
+            }
+            if (!capped && rounds_enqueued < completed + 2 * per_launch) {
                 if (int rc = enqueue()) return rc;
                 continue;
             }
@@ -2089,10 +2114,12 @@ NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, 
                 std::this_thread::yield();
             }
         }
-        const uint32_t blocks = (uint32_t)((n_total + 255) / 256);
-        k_resolve<<<blocks, 256, 0, stream>>>(d_jobs, d_js, lin, 0, (uint32_t)n_total);
+        if (!suspended) {
+            const uint32_t blocks = (uint32_t)((n_total + 255) / 256);
+            k_resolve<<<blocks, 256, 0, stream>>>(d_jobs, d_js, lin, 0, (uint32_t)n_total);
+        }
     }
-    k_finalize<<<(n_jobs + 255) / 256, 256, 0, stream>>>(d_jobs, d_js, 0, n_jobs);
+    if (!suspended) k_finalize<<<(n_jobs + 255) / 256, 256, 0, stream>>>(d_jobs, d_js, 0, n_jobs);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(ev1, stream));
     std::vector<JobState> hs(n_jobs);
@@ -2125,7 +2152,20 @@ NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, 
             stats[j].round_kernel_ms = round_ms;
         }
     }
-    return NH_OK;
+    return suspended ? NH_SUSPENDED : NH_OK;
+}
+
+} // namespace
+
+NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint64_t workspace_bytes,
+                        const nh_config *cfg, nh_stats *stats, void *stream) {
+    return batch_run_impl(jobs, n_jobs, d_workspace, workspace_bytes, cfg, stats, stream, false);
+}
+
+NH_API int nh_batch_resume(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint64_t workspace_bytes,
+                           const nh_config *cfg, nh_stats *stats, void *stream) {
+    if (n_jobs == 0) return fail(NH_EINVAL, "no jobs to resume");
+    return batch_run_impl(jobs, n_jobs, d_workspace, workspace_bytes, cfg, stats, stream, true);
 }
 
 NH_API int nh_simulate_device(const nh_scenario *scenario, uint64_t seed, const uint64_t *d_sample_ids, uint64_t n,

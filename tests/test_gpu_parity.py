@@ -319,6 +319,66 @@ def test_solo_tails_never_change_results(B, torch_mod):
                 assert np.array_equal(a, b)
 
 
+def test_checkpoint_resume_equals_uninterrupted(B, torch_mod):
+    """A run suspended between rounds, its workspace copied to the host, the device copy destroyed
+    and the bytes restored (in place, then into another buffer) finishes with bitwise the same ids,
+    richness and event counts as an uninterrupted run; a multi-job batch also resumes under other
+    tuning knobs."""
+    torch = torch_mod
+    dev = torch.device("cuda:0")
+    wl = W.config2()
+    scn = B.Scenario.from_workload(wl)
+    n = len(wl.samples)
+    s = torch.from_numpy(wl.samples.astype(np.int64)).to(dev)
+    nbytes = B.workspace_bytes(n, 1)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    ref = torch.empty(n, dtype=torch.int64, device=dev)
+    rich_ref = torch.zeros(1, dtype=torch.int64, device=dev)
+    st_ref = B.batch_run([(scn, 42, s, ref, rich_ref)], ws)[0]
+    assert not st_ref["suspended"]
+    out = torch.empty(n, dtype=torch.int64, device=dev)
+    rich = torch.zeros(1, dtype=torch.int64, device=dev)
+    job = [(scn, 42, s, out, rich)]
+    cap = B.make_config(max_rounds=3)
+    st = B.batch_run(job, ws, cap)[0]
+    say("checkpoint: suspended after", st["rounds"], "rounds")
+    assert st["suspended"] and 3 <= st["rounds"] < st_ref["rounds"]
+    host = ws.cpu()
+    ws.fill_(0xA5)  # the device copy is gone
+    ws.copy_(host.to(dev))
+    st = B.batch_resume(job, ws, cap)[0]
+    assert st["suspended"] and st["rounds"] < st_ref["rounds"]
+    host = ws.cpu()
+    ws.fill_(0x5A)
+    ws2 = torch.empty(nbytes + 512, dtype=torch.uint8, device=dev)[256:256 + nbytes]  # another buffer
+    assert ws2.data_ptr() != ws.data_ptr() and ws2.data_ptr() % 256 == 0
+    ws2.copy_(host.to(dev))
+    st = B.batch_resume(job, ws2)[0]
+    assert not st["suspended"] and st["rounds"] == st_ref["rounds"]
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref) and int(rich.item()) == int(rich_ref.item())
+    assert st["events"] == st_ref["events"] and st["merged"] == st_ref["merged"]
+    # several jobs, resumed with other knobs (knobs never change results)
+    wls = W.config4()[:6] + [SMALL[k] for k in (0, 4)]
+    for w in wls:
+        if w.samples is None:
+            w.samples = np.arange(int(w.capacity.astype(np.uint64).sum()), dtype=np.uint64)
+    scns = [B.Scenario.from_workload(w) for w in wls]
+    ss = [torch.from_numpy(w.samples.astype(np.int64)).to(dev) for w in wls]
+    n_total = sum(len(w.samples) for w in wls)
+    wsb = torch.empty(B.workspace_bytes(n_total, len(wls)), dtype=torch.uint8, device=dev)
+    outs_a = [torch.empty(len(w.samples), dtype=torch.int64, device=dev) for w in wls]
+    B.batch_run([(scns[k], wls[k].seeds[0], ss[k], outs_a[k], None) for k in range(len(wls))], wsb)
+    outs_b = [torch.empty(len(w.samples), dtype=torch.int64, device=dev) for w in wls]
+    jobs_b = [(scns[k], wls[k].seeds[0], ss[k], outs_b[k], None) for k in range(len(wls))]
+    st = B.batch_run(jobs_b, wsb, B.make_config(max_rounds=5, rounds_per_graph=1))
+    assert st[0]["suspended"]
+    st = B.batch_resume(jobs_b, wsb, B.make_config(block_size=128, blocks_per_cu=2, solo_max=64))
+    assert not st[0]["suspended"]
+    for a, b in zip(outs_a, outs_b):
+        assert torch.equal(a, b)
+
+
 def test_batch_with_empty_and_duplicate_jobs_and_device_entry_point(B, torch_mod):
     """Empty jobs inside a batch, the same job twice, and nh_simulate_device agree with the plain form."""
     import ctypes as C

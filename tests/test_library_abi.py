@@ -93,3 +93,8 @@ def test_isolated_deme_in_per_deme_mode_is_rejected(B):
     with pytest.raises(B.NecsimError) as e:
         B.Scenario(cap, w, 0.1, mode=1)
     assert "habitable mass" in str(e.value)
+
+
+def test_resume_rejects_bad_calls_before_touching_the_gpu(B):
+    assert B.nh_batch_resume(None, 0, None, 0, None, None, None) == B.NH_EINVAL
+    assert B.nh_batch_resume(None, 1, None, 0, None, None, None) == B.NH_EINVAL
