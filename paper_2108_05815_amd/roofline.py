@@ -28,9 +28,10 @@ CLOCK_HZ = 2.4e9
 PEAK_LANE_OPS = N_CU * LANES_PER_CU_CLK * CLOCK_HZ  # 3.93e13 lane-ops/s
 
 
-# Per-deme dispersal (heterogeneous habitat): per dispersal one 16-byte alias entry, the deme's two
-# row pointers (8 B) and the target's capacity (4 B) are gathered from HBM-resident tables.
-BYTES_PER_DISPERSAL_PER_DEME = 28
+# Per-deme dispersal (heterogeneous habitat): per dispersal one 16-byte alias entry (which also
+# carries both candidate targets' capacities) and the deme's two row pointers (8 B) are gathered
+# from HBM-resident tables.
+BYTES_PER_DISPERSAL_PER_DEME = 24
 
 
 def algorithmic_ops(philox_calls: int, exp_draws: int, events: int) -> float:

@@ -379,6 +379,25 @@ def test_checkpoint_resume_equals_uninterrupted(B, torch_mod):
         assert torch.equal(a, b)
 
 
+def test_timed_out_run_fails_cleanly_and_reruns_bitwise(B, torch_mod):
+    """A run stopped by its wall-clock limit (forced from the host: every kernel still finishes its
+    round) reports NH_ETIMEOUT; the same call afterwards gives the uninterrupted result."""
+    torch = torch_mod
+    dev = torch.device("cuda:0")
+    wl = W.config2()
+    scn = B.Scenario.from_workload(wl)
+    n = len(wl.samples)
+    s = torch.from_numpy(wl.samples.astype(np.int64)).to(dev)
+    ws = torch.empty(B.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
+    out = torch.empty(n, dtype=torch.int64, device=dev)
+    with pytest.raises(B.NecsimError) as e:
+        B.batch_run([(scn, 9, s, out, None)], ws, B.make_config(timeout_s=1e-9))
+    assert e.value.code == B.NH_ETIMEOUT
+    B.batch_run([(scn, 9, s, out, None)], ws)
+    ref, _, _ = B.simulate(scn, 9, wl.samples)
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), ref)
+
+
 def test_batch_with_empty_and_duplicate_jobs_and_device_entry_point(B, torch_mod):
     """Empty jobs inside a batch, the same job twice, and nh_simulate_device agree with the plain form."""
     import ctypes as C
