@@ -130,7 +130,19 @@ typedef struct {
     double round_kernel_ms;  /* HIP-event time of all round launches (cfg.event_timing), else 0 */
 } nh_stats;
 
-/* One simulate request of a batch.  Device pointers; species_out has n slots. */
+/* One simulate request of a batch.  Device pointers; species_out has n slots.
+ * Optional reporters (each may be NULL; zero-initialise the struct):
+ * - speciation events (chapter "The Declaration of Independence", the species
+ *   identity is hashed from the speciation event): d_spec_loc_out[n] (u32
+ *   location (y*W + x)*C_max + i) and d_spec_time_out[n] (f64 time) receive, per
+ *   sample, the event at which its lineage (or the lineage it coalesced with)
+ *   speciated, so species_out[q] is the species hash of exactly that event;
+ *   both or neither.
+ * - species abundance (the community's species-abundance distribution, the
+ *   output beside richness): d_abundance_ids_out[n] and d_abundance_counts_out[n]
+ *   receive one (species id, number of samples) pair per species, in no
+ *   particular order; the number of pairs written is the richness.  Both or
+ *   neither. */
 typedef struct {
     const nh_scenario *scenario;
     uint64_t seed;
@@ -138,6 +150,10 @@ typedef struct {
     uint64_t n;
     uint64_t *d_species_out;
     uint64_t *d_richness_out; /* one u64, may be NULL */
+    uint32_t *d_spec_loc_out;
+    double *d_spec_time_out;
+    uint64_t *d_abundance_ids_out;
+    uint32_t *d_abundance_counts_out;
 } nh_job;
 
 /* Builds the scenario's tables on the host (Vose alias tables, capacity prefix)

@@ -60,7 +60,9 @@ class nh_stats(C.Structure):
 
 class nh_job(C.Structure):
     _fields_ = [("scenario", C.c_void_p), ("seed", C.c_uint64), ("d_sample_ids", C.c_void_p), ("n", C.c_uint64),
-                ("d_species_out", C.c_void_p), ("d_richness_out", C.c_void_p)]
+                ("d_species_out", C.c_void_p), ("d_richness_out", C.c_void_p), ("d_spec_loc_out", C.c_void_p),
+                ("d_spec_time_out", C.c_void_p), ("d_abundance_ids_out", C.c_void_p),
+                ("d_abundance_counts_out", C.c_void_p)]
 
 
 class nh_server_config(C.Structure):
@@ -233,7 +235,10 @@ def workspace_bytes(n_total: int, n_jobs: int) -> int:
     return int(_lib.nh_workspace_bytes(n_total, n_jobs))
 
 
-def _job(scn, seed, samples, out, rich) -> nh_job:
+def _job(scn, seed, samples, out, rich, reporters=None) -> nh_job:
+    """reporters (optional dict of device tensors with one slot per sample): spec_loc (int32),
+    spec_time (float64): the speciation event behind each sample's species; abundance_ids (int64),
+    abundance_counts (int32): one (species, samples) pair per species, richness of them written."""
     j = nh_job()
     j.scenario = scn.handle
     j.seed = int(seed) & (2**64 - 1)
@@ -241,6 +246,14 @@ def _job(scn, seed, samples, out, rich) -> nh_job:
     j.n = samples.numel()
     j.d_species_out = out.data_ptr() if out.numel() else None
     j.d_richness_out = rich.data_ptr() if rich is not None else None
+    r = reporters or {}
+    for field, key in (("d_spec_loc_out", "spec_loc"), ("d_spec_time_out", "spec_time"),
+                       ("d_abundance_ids_out", "abundance_ids"), ("d_abundance_counts_out", "abundance_counts")):
+        t = r.get(key)
+        if t is not None:
+            if t.numel() < samples.numel():
+                raise ValueError(f"reporter {key} needs {samples.numel()} slots")
+            setattr(j, field, t.data_ptr() if t.numel() else None)
     return j
 
 
@@ -267,10 +280,10 @@ class Server:
         self._held = {}
         self._buf = (nh_completion * 512)()
 
-    def submit(self, tag: int, scenario: Scenario, seed: int, samples, out, rich=None, keep=None):
-        j = _job(scenario, seed, samples, out, rich)
+    def submit(self, tag: int, scenario: Scenario, seed: int, samples, out, rich=None, keep=None, reporters=None):
+        j = _job(scenario, seed, samples, out, rich, reporters)
         _check(_lib.nh_server_submit(self._h, C.byref(j), tag), "nh_server_submit")
-        self._held[tag] = (scenario, samples, out, rich, keep)
+        self._held[tag] = (scenario, samples, out, rich, keep, reporters)
 
     def progress(self) -> tuple[int, int]:
         a, p = C.c_uint32(), C.c_uint32()
@@ -308,8 +321,8 @@ def _batch(fn, name, jobs, workspace, config, stream):
     import torch
 
     arr = (nh_job * len(jobs))()
-    for k, (scn, seed, samples, out, rich) in enumerate(jobs):
-        arr[k] = _job(scn, seed, samples, out, rich)
+    for k, job in enumerate(jobs):
+        arr[k] = _job(*job)
     st = (nh_stats * len(jobs))()
     s = stream if stream is not None else torch.cuda.current_stream()
     rc = fn(arr, len(jobs), workspace.data_ptr(), workspace.numel(), C.byref(config) if config is not None else None,
@@ -323,7 +336,7 @@ def batch_run(jobs, workspace, config: nh_config | None = None, stream=None):
     """nh_batch_run over device buffers.
 
     jobs: list of (Scenario, seed, samples_tensor u64/int64 on the device, species_out tensor,
-    richness_out tensor or None).  workspace: a uint8 device tensor of at least
+    richness_out tensor or None[, reporters dict as for _job]).  workspace: a uint8 device tensor of at least
     workspace_bytes(sum n, len(jobs)) bytes.  stream: a torch.cuda.Stream or None (current stream).
     Returns the list of per-job stats dicts; each has suspended=True if config.max_rounds stopped
     the run (continue it with batch_resume)."""

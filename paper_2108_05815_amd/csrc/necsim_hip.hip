@@ -95,6 +95,13 @@ struct JobDev {
     uint32_t mode, n_shared, cap_const, rich_mask;
     uint32_t lin_base, n, start_round;
     uint32_t caps_in_table; // per-deme entries hold both targets' capacities (every capacity < 2^16)
+    // reporters (nullable): speciation event per sample, (species, samples) pairs
+    uint32_t *spec_loc_out;
+    double *spec_time_out;
+    unsigned long long *abund_ids_out;
+    uint32_t *abund_counts_out;
+    uint32_t *rich_counts;   // samples per slot of rich_set (abundance reporter)
+    uint64_t rich_off;       // offset of rich_set in the run's species-set area
 };
 
 // Per-job counters, written by the kernels.
@@ -110,6 +117,8 @@ struct JobState {
     uint32_t solo_round;  // first round of the job's solo schedule (0: not solo)
     uint32_t solo_pad;
     double h_base;        // the job's horizon in round solo_round - 1
+    uint32_t abund_n;     // abundance pairs written
+    uint32_t sentinel_count; // samples whose species id equals the set's empty marker
 };
 
 // Run control block (device memory, inside the workspace).
@@ -138,6 +147,8 @@ struct Lin {
     unsigned long long *species;
     uint32_t *job;
     uint32_t *events;
+    uint32_t *spec_loc;   // location and time of the lineage's speciation event
+    double *spec_t;
     uint32_t *act[2];
     unsigned long long *hash;
     uint32_t hmask;
@@ -798,6 +809,8 @@ __global__ void k_setup(Ctl *ctl, JobState *js, const JobDev *jobs, uint32_t n_j
         js[j].merged = 0;
         js[j].solo_round = 0;
         js[j].h_base = 0.0;
+        js[j].abund_n = 0;
+        js[j].sentinel_count = 0;
     }
 }
 
@@ -922,6 +935,8 @@ __global__ void k_init(Ctl *ctl, const JobDev *__restrict__ jobs, uint32_t n_job
         lin.t[r & 1][g] = t;
         lin.parent[g] = g;
         lin.species[g] = 0;
+        lin.spec_loc[g] = 0;
+        lin.spec_t[g] = 0.0;
         lin.job[g] = jb;
         lin.events[g] = 0;
     }
@@ -951,8 +966,13 @@ __global__ void k_job_setup(Ctl *ctl, JobDev *jobs, JobState *js, uint32_t slot)
         js[slot].merged = 0;
         js[slot].solo_round = 0;
         js[slot].h_base = 0.0;
+        js[slot].abund_n = 0;
+        js[slot].sentinel_count = 0;
     }
-    for (uint64_t i = tid; i <= (uint64_t)J->rich_mask; i += (uint64_t)gridDim.x * blockDim.x) J->rich_set[i] = ~0ull;
+    for (uint64_t i = tid; i <= (uint64_t)J->rich_mask; i += (uint64_t)gridDim.x * blockDim.x) {
+        J->rich_set[i] = ~0ull;
+        J->rich_counts[i] = 0u;
+    }
 }
 
 // Round kernels.  Round r takes the queue of round r, drops lineages whose
@@ -1113,6 +1133,8 @@ __device__ __forceinline__ void round_one_lane(const RoundArgs &A, uint32_t r, u
         }
         if (finish_dead) {
             lin.species[g] = speciated ? species_of(v, p.loc, t) : 0ull;
+            lin.spec_loc[g] = p.loc;
+            lin.spec_t[g] = t;
             lin.events[g] += ev;
             has = false;
         }
@@ -1234,6 +1256,8 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
         if (finish_dead) {
             if (leader) {
                 lin.species[g] = speciated ? species_of(v, p.loc, t) : 0ull;
+                lin.spec_loc[g] = p.loc;
+                lin.spec_t[g] = t;
                 lin.events[g] += ev;
             }
             has = false;
@@ -1345,12 +1369,21 @@ __global__ void k_resolve(const JobDev *__restrict__ jobs, JobState *js, Lin lin
         uint32_t x = g;
         while (lin.parent[x] != x) x = lin.parent[x];
         const unsigned long long sp = lin.species[x];
-        J->species_out[g - J->lin_base] = sp;
+        const uint32_t q = g - J->lin_base;
+        J->species_out[q] = sp;
+        if (J->spec_time_out) {
+            J->spec_loc_out[q] = lin.spec_loc[x];
+            J->spec_time_out[q] = lin.spec_t[x];
+        }
         events = lin.events[g];
         is_root = x == g;
-        if (is_root) {
+        // Representatives insert their species into the job's set; with the abundance reporter
+        // every sample inserts-or-finds its species and counts itself at its slot.
+        const bool count = J->abund_counts_out != nullptr;
+        if (is_root || count) {
             if (sp == ~0ull) {
-                atomicOr(&js[jb].flags, kJobSentinelSpecies);
+                if (is_root) atomicOr(&js[jb].flags, kJobSentinelSpecies);
+                if (count) atomicAdd(&js[jb].sentinel_count, 1u);
             } else {
                 uint32_t idx = (uint32_t)sp & J->rich_mask;
                 for (uint32_t probe = 0; probe <= J->rich_mask; ++probe) {
@@ -1363,6 +1396,7 @@ __global__ void k_resolve(const JobDev *__restrict__ jobs, JobState *js, Lin lin
                     if (cur == sp) break;
                     idx = (idx + 1u) & J->rich_mask;
                 }
+                if (count) atomicAdd(&J->rich_counts[idx], 1u);
             }
         }
     }
@@ -1385,12 +1419,43 @@ __global__ void k_resolve(const JobDev *__restrict__ jobs, JobState *js, Lin lin
     }
 }
 
+// Abundance reporter: every occupied slot of the species sets of jobs
+// [j_lo, j_hi) (contiguous in the species-set area, n_slots in all) appends its
+// (species, samples) pair to its job's output.
+__global__ void k_abundance(const JobDev *__restrict__ jobs, JobState *js, uint32_t j_lo, uint32_t j_hi,
+                            uint64_t n_slots) {
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_slots) return;
+    const uint64_t base = jobs[j_lo].rich_off;
+    uint32_t lo = j_lo, hi = j_hi; // the last job whose set starts at or before slot s
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (jobs[mid].rich_off - base <= s) lo = mid;
+        else hi = mid;
+    }
+    const JobDev *J = &jobs[lo];
+    if (!J->abund_counts_out) return;
+    const uint64_t local = s - (J->rich_off - base);
+    if (local > J->rich_mask) return;
+    const unsigned long long id = J->rich_set[local];
+    if (id == ~0ull) return;
+    const uint32_t at = atomicAdd(&js[lo].abund_n, 1u);
+    J->abund_ids_out[at] = id;
+    J->abund_counts_out[at] = J->rich_counts[local];
+}
+
 __global__ void k_finalize(const JobDev *__restrict__ jobs, JobState *js, uint32_t j_begin, uint32_t j_end) {
     const uint32_t j = j_begin + blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= j_end) return;
-    const unsigned long long rich = js[j].rich_count + ((js[j].flags & kJobSentinelSpecies) ? 1ull : 0ull);
+    const bool sentinel = (js[j].flags & kJobSentinelSpecies) != 0u;
+    const unsigned long long rich = js[j].rich_count + (sentinel ? 1ull : 0ull);
     js[j].rich_count = rich;
     if (jobs[j].richness_out) *jobs[j].richness_out = rich;
+    if (sentinel && jobs[j].abund_counts_out) {
+        const uint32_t at = js[j].abund_n++;
+        jobs[j].abund_ids_out[at] = ~0ull;
+        jobs[j].abund_counts_out[at] = js[j].sentinel_count;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1569,7 +1634,7 @@ void scenario_free(nh_scenario *s) {
 
 struct Workspace {
     uint64_t off_ctl, off_jobs, off_js, off_ring, off_htab, off_loc0, off_loc1, off_t0, off_t1, off_parent, off_species,
-        off_job, off_events, off_act0, off_act1, off_hash, off_rich, total;
+        off_job, off_events, off_sloc, off_st, off_act0, off_act1, off_hash, off_rich, off_rcount, total;
     uint64_t hcap;
 };
 
@@ -1595,11 +1660,14 @@ Workspace layout(uint64_t n_total, uint32_t n_jobs) {
     w.off_species = take(8 * N);
     w.off_job = take(4 * N);
     w.off_events = take(4 * N);
+    w.off_sloc = take(4 * N);
+    w.off_st = take(8 * N);
     w.off_act0 = take(4 * N);
     w.off_act1 = take(4 * N);
     w.hcap = pow2_at_least(2 * N, 1024);
     w.off_hash = take(8 * w.hcap);
     w.off_rich = take(8 * (4 * N + 64ull * std::max<uint32_t>(n_jobs, 1)));
+    w.off_rcount = take(4 * (4 * N + 64ull * std::max<uint32_t>(n_jobs, 1)));
     w.total = o;
     return w;
 }
@@ -1850,6 +1918,8 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
         if (!jb.scenario) return fail(NH_EINVAL, "job %u has no scenario", j);
         if (jb.n > 0 && (!jb.d_sample_ids || !jb.d_species_out))
             return fail(NH_EINVAL, "job %u has NULL sample or output buffers", j);
+        if (!jb.d_spec_loc_out != !jb.d_spec_time_out || !jb.d_abundance_ids_out != !jb.d_abundance_counts_out)
+            return fail(NH_EINVAL, "job %u: reporter outputs come in pairs (both or neither)", j);
         n_total += jb.n;
     }
     if (n_total >= (1ull << 31)) return fail(NH_EINVAL, "more than 2^31 - 1 samples in one batch");
@@ -1875,15 +1945,19 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
     lin.species = (unsigned long long *)(ws + L.off_species);
     lin.job = (uint32_t *)(ws + L.off_job);
     lin.events = (uint32_t *)(ws + L.off_events);
+    lin.spec_loc = (uint32_t *)(ws + L.off_sloc);
+    lin.spec_t = (double *)(ws + L.off_st);
     lin.act[0] = (uint32_t *)(ws + L.off_act0);
     lin.act[1] = (uint32_t *)(ws + L.off_act1);
     lin.hash = (unsigned long long *)(ws + L.off_hash);
     lin.hmask = (uint32_t)(L.hcap - 1);
     unsigned long long *rich = (unsigned long long *)(ws + L.off_rich);
+    uint32_t *rich_counts = (uint32_t *)(ws + L.off_rcount);
 
     // Job descriptors.
     std::vector<JobDev> hj(n_jobs);
     uint64_t base = 0, rich_off = 0;
+    bool any_abundance = false;
     bool all_same_scenario = true;
     for (uint32_t j = 0; j < n_jobs; ++j) {
         const nh_scenario *s = jobs[j].scenario;
@@ -1904,8 +1978,15 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
         d.richness_out = (unsigned long long *)jobs[j].d_richness_out;
         const uint64_t slots = pow2_at_least(2 * jobs[j].n, 64);
         d.rich_set = rich + rich_off;
+        d.rich_counts = rich_counts + rich_off;
+        d.rich_off = rich_off;
         d.rich_mask = (uint32_t)(slots - 1);
         rich_off += slots;
+        d.spec_loc_out = jobs[j].d_spec_loc_out;
+        d.spec_time_out = jobs[j].d_spec_time_out;
+        d.abund_ids_out = (unsigned long long *)jobs[j].d_abundance_ids_out;
+        d.abund_counts_out = jobs[j].d_abundance_counts_out;
+        if (d.abund_counts_out) any_abundance = true;
         d.n_individuals = s->N;
         d.W = s->W;
         d.H = s->H;
@@ -1961,6 +2042,7 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
                                                                                  base_round);
         k_fill_u64<<<1024, 256, 0, stream>>>(lin.hash, L.hcap, 0ull);
         if (rich_off) k_fill_u64<<<1024, 256, 0, stream>>>(rich, rich_off, ~0ull);
+        if (rich_off) k_fill_u64<<<1024, 256, 0, stream>>>((unsigned long long *)rich_counts, rich_off / 2, 0ull);
         if (n_total) {
             const uint32_t blocks = (uint32_t)((n_total + 255) / 256);
             k_init<<<blocks, 256, 0, stream>>>(ctl, d_jobs, n_jobs, -1, d_js, d_ring, ring_cap, lin, 0,
@@ -2117,6 +2199,9 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
         if (!suspended) {
             const uint32_t blocks = (uint32_t)((n_total + 255) / 256);
             k_resolve<<<blocks, 256, 0, stream>>>(d_jobs, d_js, lin, 0, (uint32_t)n_total);
+            if (any_abundance)
+                k_abundance<<<(uint32_t)((rich_off + 255) / 256), 256, 0, stream>>>(d_jobs, d_js, 0, n_jobs,
+                                                                                    rich_off);
         }
     }
     if (!suspended) k_finalize<<<(n_jobs + 255) / 256, 256, 0, stream>>>(d_jobs, d_js, 0, n_jobs);
@@ -2284,6 +2369,7 @@ struct nh_server {
     double *d_htab = nullptr;
     Lin lin{};
     unsigned long long *rich = nullptr;
+    uint32_t *rich_counts = nullptr;
     uint64_t rich_total = 0;
     // host-mapped / pinned
     unsigned long long *status_h = nullptr, *status_d = nullptr;
@@ -2321,8 +2407,8 @@ void server_free(nh_server *s) {
     delete s;
 }
 
-void job_descriptor(JobDev &d, const nh_job &job, unsigned long long *rich_set, uint64_t rich_slots,
-                    uint64_t lin_base) {
+void job_descriptor(JobDev &d, const nh_job &job, unsigned long long *rich_set, uint32_t *rich_counts,
+                    uint64_t rich_off, uint64_t rich_slots, uint64_t lin_base) {
     const nh_scenario *sc = job.scenario;
     std::memset(&d, 0, sizeof d);
     d.seed = job.seed;
@@ -2338,7 +2424,13 @@ void job_descriptor(JobDev &d, const nh_job &job, unsigned long long *rich_set, 
     d.species_out = (unsigned long long *)job.d_species_out;
     d.richness_out = (unsigned long long *)job.d_richness_out;
     d.rich_set = rich_set;
+    d.rich_counts = rich_counts;
+    d.rich_off = rich_off;
     d.rich_mask = (uint32_t)(rich_slots - 1);
+    d.spec_loc_out = job.d_spec_loc_out;
+    d.spec_time_out = job.d_spec_time_out;
+    d.abund_ids_out = (unsigned long long *)job.d_abundance_ids_out;
+    d.abund_counts_out = job.d_abundance_counts_out;
     d.n_individuals = sc->N;
     d.W = sc->W;
     d.H = sc->H;
@@ -2382,7 +2474,7 @@ int server_admit(nh_server *s, const nh_job &job, uint64_t tag, bool &admitted) 
     sl.rich_base = rich_at;
     sl.rich_slots = rich_slots;
     JobDev &d = s->jobdev_h[slot];
-    job_descriptor(d, job, s->rich + rich_at, rich_slots, lin_at);
+    job_descriptor(d, job, s->rich + rich_at, s->rich_counts + rich_at, rich_at, rich_slots, lin_at);
     HIP_TRY(hipMemcpyAsync(&s->d_jobs[slot], &d, sizeof(JobDev), hipMemcpyHostToDevice, s->stream));
     const uint32_t fill_blocks = (uint32_t)std::min<uint64_t>(1024, (rich_slots + 255) / 256);
     k_job_setup<<<fill_blocks, 256, 0, s->stream>>>(s->ctl, s->d_jobs, s->d_js, slot);
@@ -2456,11 +2548,14 @@ NH_API int nh_server_create(const nh_server_config *config, void *stream, nh_ser
     s->lin.species = (unsigned long long *)(ws + s->L.off_species);
     s->lin.job = (uint32_t *)(ws + s->L.off_job);
     s->lin.events = (uint32_t *)(ws + s->L.off_events);
+    s->lin.spec_loc = (uint32_t *)(ws + s->L.off_sloc);
+    s->lin.spec_t = (double *)(ws + s->L.off_st);
     s->lin.act[0] = (uint32_t *)(ws + s->L.off_act0);
     s->lin.act[1] = (uint32_t *)(ws + s->L.off_act1);
     s->lin.hash = (unsigned long long *)(ws + s->L.off_hash);
     s->lin.hmask = (uint32_t)(s->L.hcap - 1);
     s->rich = (unsigned long long *)(ws + s->L.off_rich);
+    s->rich_counts = (uint32_t *)(ws + s->L.off_rcount);
     s->rich_total = 4 * s->cap_lin + 64ull * s->max_jobs;
     void *h = nullptr;
     if (hipHostMalloc(&h, 256, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
@@ -2540,6 +2635,8 @@ NH_API int nh_server_submit(nh_server *s, const nh_job *job, uint64_t tag) {
     if (!s || !job || !job->scenario) return fail(NH_EINVAL, "NULL server, job or scenario");
     if (job->n > 0 && (!job->d_sample_ids || !job->d_species_out))
         return fail(NH_EINVAL, "NULL sample or output buffer");
+    if (!job->d_spec_loc_out != !job->d_spec_time_out || !job->d_abundance_ids_out != !job->d_abundance_counts_out)
+        return fail(NH_EINVAL, "reporter outputs come in pairs (both or neither)");
     if (job->n > s->cap_lin)
         return fail(NH_EINVAL, "job of %llu lineages exceeds the server capacity %llu", (unsigned long long)job->n,
                     (unsigned long long)s->cap_lin);
@@ -2561,6 +2658,9 @@ NH_API int nh_server_progress(nh_server *s, uint32_t *active_out, uint32_t *pend
         const uint32_t blocks = (uint32_t)((sl.n + 255) / 256);
         k_resolve<<<blocks, 256, 0, s->stream>>>(s->d_jobs, s->d_js, s->lin, (uint32_t)sl.lin_base,
                                                   (uint32_t)(sl.lin_base + sl.n));
+        if (sl.job.d_abundance_counts_out)
+            k_abundance<<<(uint32_t)((sl.rich_slots + 255) / 256), 256, 0, s->stream>>>(s->d_jobs, s->d_js, slot,
+                                                                                      slot + 1, sl.rich_slots);
         k_finalize<<<1, 1, 0, s->stream>>>(s->d_jobs, s->d_js, slot, slot + 1);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(&s->js_h[slot], &s->d_js[slot], sizeof(JobState), hipMemcpyDeviceToHost, s->stream));

@@ -15,6 +15,7 @@ import pytest
 
 import oracle
 from paper_2108_05815_amd import workloads as W
+from reporters_check import check_reporters
 
 pytestmark = pytest.mark.gpu
 
@@ -396,6 +397,43 @@ def test_timed_out_run_fails_cleanly_and_reruns_bitwise(B, torch_mod):
     B.batch_run([(scn, 9, s, out, None)], ws)
     ref, _, _ = B.simulate(scn, 9, wl.samples)
     assert np.array_equal(out.cpu().numpy().view(np.uint64), ref)
+
+
+def _reporters(torch, n, dev):
+    return {"spec_loc": torch.empty(n, dtype=torch.int32, device=dev),
+            "spec_time": torch.empty(n, dtype=torch.float64, device=dev),
+            "abundance_ids": torch.empty(n, dtype=torch.int64, device=dev),
+            "abundance_counts": torch.empty(n, dtype=torch.int32, device=dev)}
+
+
+def test_reporters_match_the_oracle_and_the_species(B, torch_mod):
+    """Speciation-event and abundance reporters in one batch of mixed scenarios."""
+    torch = torch_mod
+    dev = torch.device("cuda:0")
+    wls = [SMALL[k] for k in (0, 1, 2, 3, 4, 5, 8)]
+    samples = [np.arange(int(w.capacity.astype(np.uint64).sum()), dtype=np.uint64) for w in wls]
+    scns = [B.Scenario.from_workload(w) for w in wls]
+    ss = [torch.from_numpy(x.astype(np.int64)).to(dev) for x in samples]
+    outs = [torch.empty(len(x), dtype=torch.int64, device=dev) for x in samples]
+    rich = torch.zeros(len(wls), dtype=torch.int64, device=dev)
+    reps = [_reporters(torch, len(x), dev) for x in samples]
+    jobs = [(scns[k], wls[k].seeds[0], ss[k], outs[k], rich[k:k + 1], reps[k]) for k in range(len(wls))]
+    n_total = sum(len(x) for x in samples)
+    ws = torch.empty(B.workspace_bytes(n_total, len(wls)), dtype=torch.uint8, device=dev)
+    B.batch_run(jobs, ws)
+    torch.cuda.synchronize()
+    for k, w in enumerate(wls):
+        say("reporters:", w.name)
+        sp = outs[k].cpu().numpy().view(np.uint64)
+        osc = oracle.Scenario(w.capacity, w.weights, w.nu, mode=w.mode)
+        ref, _, _ = osc.simulate_culled(w.seeds[0], samples[k], 2.0)
+        assert np.array_equal(sp, ref)
+        check_reporters(sp, int(rich[k].item()), reps[k], w.seeds[0], osc, samples[k])
+    # pairs must be both or neither
+    bad = dict(reps[0])
+    bad["spec_time"] = None
+    with pytest.raises(B.NecsimError):
+        B.batch_run([(scns[0], 1, ss[0], outs[0], None, bad)], ws)
 
 
 def test_batch_with_empty_and_duplicate_jobs_and_device_entry_point(B, torch_mod):

@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 from paper_2108_05815_amd import workloads as W
+from reporters_check import check_reporters
 
 pytestmark = pytest.mark.gpu
 
@@ -63,8 +64,15 @@ def test_served_results_equal_alone_and_oracle(env, solo):
             s = torch.from_numpy(wls[k].samples.astype(np.int64)).to(dev)
             o = torch.empty(len(wls[k].samples), dtype=torch.int64, device=dev)
             r = torch.zeros(1, dtype=torch.int64, device=dev)
-            srv.submit(k, scns[k], wls[k].seeds[0], s, o, r)
-            outs[k] = (o, r)
+            rep = None
+            if k % 2 == 0:  # every other job also asks for the reporters
+                n = len(wls[k].samples)
+                rep = {"spec_loc": torch.empty(n, dtype=torch.int32, device=dev),
+                       "spec_time": torch.empty(n, dtype=torch.float64, device=dev),
+                       "abundance_ids": torch.empty(n, dtype=torch.int64, device=dev),
+                       "abundance_counts": torch.empty(n, dtype=torch.int32, device=dev)}
+            srv.submit(k, scns[k], wls[k].seeds[0], s, o, r, reporters=rep)
+            outs[k] = (o, r, rep)
             submitted += 1
         srv.progress()
         for c in srv.poll():
@@ -79,6 +87,8 @@ def test_served_results_equal_alone_and_oracle(env, solo):
         alone, rich, _ = B.simulate(scns[k], w.seeds[0], w.samples)
         assert np.array_equal(got, alone), w.name
         assert int(outs[k][1].item()) == rich == c["richness"]
+        if outs[k][2] is not None:
+            check_reporters(got, rich, outs[k][2], w.seeds[0])
         say(w.name, "rounds", c["rounds"], "richness", rich)
     # oracle on the small ones
     for k in (0, 6, 8):
