@@ -162,6 +162,8 @@ def main():
     round_s = totals["round_kernel_ms"] / 1e3
     achieved = ops / round_s / 1e12 if round_s > 0 else 0.0
     peak = RL.PEAK_LANE_OPS / 1e12
+    # the rate the chip sustains for the same Philox + log mix with every lane busy (in-repo microbenchmark)
+    mix_peak = B.measure_mix_peak(stream) / 1e12
     traffic = traffic_from_profile(args.traffic)
     line = {
         "metric": METRIC,
@@ -191,6 +193,8 @@ def main():
             "unit": "T lane-ops/s",
             "frac": achieved / peak,
             "traffic": traffic,
+            "mix_peak": mix_peak,
+            "frac_of_mix_peak": achieved / mix_peak,
             "avg_launch_us": totals["round_kernel_ms"] * 1e3 / max(1, totals["round_kernels"]),
             "launches": totals["round_kernels"],
             "ops_per_launch": ops / max(1, totals["round_kernels"]),
@@ -241,11 +245,19 @@ def habitat_form(B, W, torch) -> dict:
     disp = st["events"] - st["speciated"]
     gather_bytes = disp * RL.BYTES_PER_DISPERSAL_PER_DEME
     rs = st["round_kernel_ms"] / 1e3
+    # random 16-byte gathers from a table as large as the habitat's: the ceiling those gathers could reach
+    ceiling = B.measure_gather(scn_table_sized(torch, dev, scn.table_bytes))
     return {"workload": wl.name, "lineages": n, "table_gib": scn.table_bytes / 2**30, "create_s": create_s,
             "seconds": el, "events": st["events"], "events_per_s": st["events"] / el, "individuals_per_s": n / el,
             "richness": st["richness"], "rounds": st["rounds"],
             "gather_gb_per_s": gather_bytes / rs / 1e9 if rs > 0 else None,
-            "gather_frac_of_8tbs": gather_bytes / rs / 8e12 if rs > 0 else None}
+            "gather_frac_of_8tbs": gather_bytes / rs / 8e12 if rs > 0 else None,
+            "gather_ceiling_gb_per_s": ceiling / 1e9,
+            "gather_frac_of_ceiling": gather_bytes / rs / ceiling if rs > 0 else None}
+
+
+def scn_table_sized(torch, dev, nbytes):
+    return torch.empty(max(int(nbytes), 1 << 20), dtype=torch.uint8, device=dev)
 
 
 def batched_form(args, B, W, torch) -> dict:

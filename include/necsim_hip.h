@@ -291,6 +291,20 @@ const char *nh_last_error(void);
 /* Library version string. */
 const char *nh_version(void);
 
+/* Measurement helpers, not part of the method; callers are benchmarks that
+ * price the hot path against what the chip sustains.
+ * nh_measure_mix_peak: with 8 workgroups of 256 lanes per compute unit, every
+ * lane evaluates 3 Philox4x32-10 blocks and 2 exponential-draw logarithms per
+ * iteration (about the event path's mix) from registers; *lane_ops_per_s gets
+ * the rate in the algorithmic units the path is counted in (100 per Philox
+ * block, 43 per draw).  Allocates a small sink buffer on the stream; blocks.
+ * nh_measure_gather: random 16-byte gathers from d_table (device memory of
+ * table_bytes >= 16 KiB, contents irrelevant) by the same number of lanes, 256
+ * per lane; *bytes_per_s gets the useful bytes (16 per gather) per second.
+ * Both return NH_EINVAL on NULL arguments, NH_EDEVICE on a HIP error. */
+int nh_measure_mix_peak(double *lane_ops_per_s, void *stream);
+int nh_measure_gather(const void *d_table, uint64_t table_bytes, double *bytes_per_s, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

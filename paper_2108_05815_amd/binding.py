@@ -120,6 +120,10 @@ _lib.nh_last_error.argtypes = []
 _lib.nh_last_error.restype = C.c_char_p
 _lib.nh_version.argtypes = []
 _lib.nh_version.restype = C.c_char_p
+_lib.nh_measure_mix_peak.argtypes = [C.POINTER(C.c_double), C.c_void_p]
+_lib.nh_measure_mix_peak.restype = C.c_int
+_lib.nh_measure_gather.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_double), C.c_void_p]
+_lib.nh_measure_gather.restype = C.c_int
 
 # The C names, for callers that want the raw ABI.
 nh_scenario_create = _lib.nh_scenario_create
@@ -134,6 +138,8 @@ nh_simulate_device = _lib.nh_simulate_device
 nh_simulate = _lib.nh_simulate
 nh_last_error = _lib.nh_last_error
 nh_version = _lib.nh_version
+nh_measure_mix_peak = _lib.nh_measure_mix_peak
+nh_measure_gather = _lib.nh_measure_gather
 nh_server_bytes = _lib.nh_server_bytes
 nh_server_create = _lib.nh_server_create
 nh_server_submit = _lib.nh_server_submit
@@ -146,7 +152,8 @@ EXPORTED = ["nh_scenario_create", "nh_scenario_destroy", "nh_scenario_individual
             "nh_workspace_bytes", "nh_scenario_footprint_bytes", "nh_batch_run", "nh_batch_resume",
             "nh_simulate_device",
             "nh_simulate", "nh_last_error", "nh_version", "nh_server_bytes", "nh_server_create",
-            "nh_server_submit", "nh_server_progress", "nh_server_poll", "nh_server_drain", "nh_server_destroy"]
+            "nh_server_submit", "nh_server_progress", "nh_server_poll", "nh_server_drain", "nh_server_destroy",
+            "nh_measure_mix_peak", "nh_measure_gather"]
 
 
 class NecsimError(RuntimeError):
@@ -346,3 +353,22 @@ def batch_run(jobs, workspace, config: nh_config | None = None, stream=None):
 def batch_resume(jobs, workspace, config: nh_config | None = None, stream=None):
     """nh_batch_resume: continue a suspended run from the state in `workspace` (the same jobs)."""
     return _batch(_lib.nh_batch_resume, "nh_batch_resume", jobs, workspace, config, stream)
+
+
+def measure_mix_peak(stream=None) -> float:
+    """Algorithmic lane-ops/s the chip sustains for the event path's Philox + log mix."""
+    import torch
+    x = C.c_double()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(_lib.nh_measure_mix_peak(C.byref(x), C.c_void_p(s.cuda_stream)), "nh_measure_mix_peak")
+    return x.value
+
+
+def measure_gather(table, stream=None) -> float:
+    """Useful bytes/s of random 16-byte gathers from a device tensor `table`."""
+    import torch
+    x = C.c_double()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(_lib.nh_measure_gather(table.data_ptr(), table.numel() * table.element_size(), C.byref(x),
+                                  C.c_void_p(s.cuda_stream)), "nh_measure_gather")
+    return x.value

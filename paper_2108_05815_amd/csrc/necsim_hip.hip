@@ -1459,6 +1459,50 @@ __global__ void k_finalize(const JobDev *__restrict__ jobs, JobState *js, uint32
 }
 
 // ---------------------------------------------------------------------------
+// Measurement helpers (not part of the method): the throughput the chip
+// sustains for the event path's own instruction mix with every lane busy, and
+// for random 16-byte gathers from a large table.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kMixPhilox = 3, kMixDraws = 2; // per iteration: about the event path's 1.6 blocks per draw
+
+__global__ __launch_bounds__(256) void k_peak_mix(uint32_t iters, uint64_t seed, unsigned long long *sink) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    uint32_t s0 = g, s1 = 0;
+    double acc = 0.0;
+    for (uint32_t i = 0; i < iters; ++i) {
+        uint32_t w[kMixPhilox][4];
+#pragma unroll
+        for (uint32_t b = 0; b < kMixPhilox; ++b) {
+            w[b][0] = s0;
+            w[b][1] = i;
+            w[b][2] = s1;
+            w[b][3] = b;
+            philox10(w[b][0], w[b][1], w[b][2], w[b][3], k0, k1);
+        }
+#pragma unroll
+        for (uint32_t d = 0; d < kMixDraws; ++d) acc += log_u53o(((uint64_t)w[d][1] << 32) | w[d][0]);
+        s1 ^= w[kMixPhilox - 1][2];
+    }
+    if (acc == 1.0) sink[g] = s1; // never true (a sum of logs of (0,1] draws); keeps the work live
+}
+
+__global__ __launch_bounds__(256) void k_peak_gather(const uint4 *__restrict__ table, uint64_t n_entries,
+                                                     uint32_t iters, unsigned long long *sink) {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t h = g * 0x9E3779B97F4A7C15ull + 1ull;
+    uint32_t acc = 0;
+    for (uint32_t i = 0; i < iters; ++i) {
+        h ^= h >> 31;
+        h *= 0xBF58476D1CE4E5B9ull;
+        h ^= h >> 29;
+        const uint4 e = table[mulhi_index(h, (uint32_t)min<uint64_t>(n_entries, 0xFFFFFFFFull))];
+        acc += e.x ^ e.y ^ e.z ^ e.w;
+    }
+    if (acc == 0x12345678u) sink[g] = acc; // keeps the loads live
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
@@ -1723,6 +1767,61 @@ std::vector<double> horizon_table(const nh_config &c) {
 NH_API const char *nh_last_error(void) { return g_last_error.c_str(); }
 
 NH_API const char *nh_version(void) { return "libnecsim_hip 0.1 (gfx950)"; }
+
+NH_API int nh_measure_mix_peak(double *lane_ops_per_s, void *stream_ptr) {
+    if (!lane_ops_per_s) return fail(NH_EINVAL, "NULL output");
+    hipStream_t stream = (hipStream_t)stream_ptr;
+    int dev = 0, n_cu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    const uint32_t blocks = (uint32_t)std::max(1, n_cu) * 8, threads = 256, iters = 2048;
+    unsigned long long *sink = nullptr;
+    HIP_TRY(hipMallocAsync((void **)&sink, sizeof(unsigned long long) * blocks * threads, stream));
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    k_peak_mix<<<blocks, threads, 0, stream>>>(64, 1, sink); // warm-up
+    HIP_TRY(hipEventRecord(a, stream));
+    k_peak_mix<<<blocks, threads, 0, stream>>>(iters, 2, sink);
+    HIP_TRY(hipEventRecord(b, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipFreeAsync(sink, stream);
+    const double ops_per_iter = 100.0 * kMixPhilox + 43.0 * kMixDraws;
+    *lane_ops_per_s = (double)blocks * threads * iters * ops_per_iter / (ms * 1e-3);
+    return NH_OK;
+}
+
+NH_API int nh_measure_gather(const void *d_table, uint64_t table_bytes, double *bytes_per_s, void *stream_ptr) {
+    if (!d_table || !bytes_per_s || table_bytes < 16 * 1024) return fail(NH_EINVAL, "bad gather table");
+    hipStream_t stream = (hipStream_t)stream_ptr;
+    int dev = 0, n_cu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    const uint32_t blocks = (uint32_t)std::max(1, n_cu) * 8, threads = 256, iters = 256;
+    unsigned long long *sink = nullptr;
+    HIP_TRY(hipMallocAsync((void **)&sink, sizeof(unsigned long long) * blocks * threads, stream));
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    const uint64_t n = table_bytes / 16;
+    k_peak_gather<<<blocks, threads, 0, stream>>>((const uint4 *)d_table, n, 16, sink); // warm-up
+    HIP_TRY(hipEventRecord(a, stream));
+    k_peak_gather<<<blocks, threads, 0, stream>>>((const uint4 *)d_table, n, iters, sink);
+    HIP_TRY(hipEventRecord(b, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipFreeAsync(sink, stream);
+    *bytes_per_s = (double)blocks * threads * iters * 16.0 / (ms * 1e-3);
+    return NH_OK;
+}
+
 
 NH_API int nh_scenario_create(const nh_habitat *habitat, const nh_dispersal *dispersal, double nu,
                               const nh_params *params, nh_scenario **out) {

@@ -469,3 +469,13 @@ def test_batch_with_empty_and_duplicate_jobs_and_device_entry_point(B, torch_mod
     assert rc == 0
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy().view(np.uint64), alone) and int(r1.item()) == r
+
+
+def test_measurement_helpers_report_plausible_rates(B, torch_mod):
+    """The mix-peak and gather-ceiling microbenchmarks run and give rates within physical bounds."""
+    torch = torch_mod
+    mix = B.measure_mix_peak()
+    assert 1e12 < mix < 2e14, mix  # algorithmic lane-ops/s; the VALU issues 3.9e13 instructions/s
+    table = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+    g = B.measure_gather(table)
+    assert 1e9 < g < 8e12, g
