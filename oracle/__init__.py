@@ -67,6 +67,8 @@ def _load():
         lib.or_scenario_table.restype = C.c_uint32
         lib.or_sample_location.argtypes = [C.c_void_p, C.c_uint64]
         lib.or_sample_location.restype = C.c_uint32
+        lib.or_scenario_set_sampler.argtypes = [C.c_void_p, C.c_uint32]
+        lib.or_scenario_set_sampler.restype = C.c_int
         lib.or_next_event_time.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_double]
         lib.or_next_event_time.restype = C.c_double
         lib.or_simulate_naive.argtypes = [C.c_void_p, C.c_uint64, u64p, C.c_uint64, u64p, f64p, u64p]
@@ -134,7 +136,8 @@ class Scenario:
     demes; mode 1 builds one table per habitable deme over weight x target
     capacity (zero-capacity targets dropped)."""
 
-    def __init__(self, capacity, weights, nu: float, *, mode: int = 0, lam: float = 1.0, dt: float = 1.0):
+    def __init__(self, capacity, weights, nu: float, *, mode: int = 0, lam: float = 1.0, dt: float = 1.0,
+                 sampler: int = 0):
         lib = _load()
         cap = np.ascontiguousarray(capacity, dtype=np.uint32)
         if cap.ndim != 2:
@@ -154,6 +157,9 @@ class Scenario:
             raise ValueError(f"invalid scenario ({rc})")
         self._h = h
         self._lib = lib
+        self.sampler = sampler
+        if sampler and lib.or_scenario_set_sampler(h, sampler) != 0:
+            raise ValueError("invalid event-time sampler")
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -25,7 +25,12 @@
  *   [dedup] section "Deduplicating Redundant Individuals" and the Water-Level
  *           algorithm (time-aligned rounds);
  *   [comp]  section "The Statically Checked Component System" (habitat,
- *           dispersal sampler, coalescence sampler = uniform deme index).
+ *           dispersal sampler, coalescence sampler = uniform deme index);
+ *   [hppp]  section "Homogeneous Poisson Point Process" of the Independent
+ *           Algorithm chapter (the log-free alternative to the exponential
+ *           sums: a Poisson count per interval, the events uniform in it) and
+ *           appendix "Iterative Sampling: Geometric and Poisson" (the count by
+ *           a linear search over the Poisson cdf, one uniform per count).
  */
 #include <math.h>
 #include <stdint.h>
@@ -206,7 +211,9 @@ typedef struct {
     uint64_t *prefix; /* prefix[c] = sum of cap before cell c; prefix[W H] = N */
     uint32_t cmax;
     double *weights;  /* (2R+1)^2 */
-    double nu, inv_lambda, dt, inv_dt;
+    double nu, lambda, inv_lambda, dt, inv_dt;
+    uint32_t sampler; /* 0: exponential sums; 1: Poisson count + uniform points [hppp] */
+    double mu, p0;    /* sampler 1: lambda * dt and exp(-lambda * dt) */
     or_table shared;  /* mode 0 */
     or_table **cells; /* mode 1, built on first visit */
 } or_scenario;
@@ -279,7 +286,7 @@ OR_EXPORT int or_scenario_create(uint32_t W, uint32_t H, const uint32_t *cap, ui
     or_scenario *s = (or_scenario *)calloc(1, sizeof(or_scenario));
     if (!s) return -2;
     s->W = W; s->H = H; s->R = R; s->mode = mode;
-    s->nu = nu; s->inv_lambda = 1.0 / lambda; s->dt = dt; s->inv_dt = 1.0 / dt;
+    s->nu = nu; s->lambda = lambda; s->inv_lambda = 1.0 / lambda; s->dt = dt; s->inv_dt = 1.0 / dt;
     uint64_t cells = (uint64_t)W * H;
     uint32_t side = 2 * R + 1;
     s->cap = (uint32_t *)malloc(sizeof(uint32_t) * cells);
@@ -376,7 +383,54 @@ static uint64_t interval_draw(uint64_t seed, uint32_t loc, uint64_t k, uint32_t 
     return (j & 1u) ? b : a;
 }
 
+/* [hppp] The events of interval k at loc are a Poisson(mu = lambda dt)    */
+/* number of points, uniform in [k dt, (k+1) dt): draw 0 of the interval's  */
+/* stream gives the count by inverting the Poisson cdf with a linear search  */
+/* (p_0 = exp(-mu), p_n = p_{n-1} mu / n, stop at the first n whose         */
+/* cumulative sum reaches u; also stop if p_n underflows to 0), draws        */
+/* 1 .. N place the points at k dt + U(r) dt.  The next event after t_last  */
+/* is the smallest point beyond it; an interval without one moves the        */
+/* search to interval k+1.  Needs mu <= 700 so that exp(-mu) is normal.      */
+static uint32_t poisson_count(const or_scenario *s, double u) {
+    double p = s->p0, cdf = p;
+    uint32_t n = 0;
+    while (u > cdf && p > 0.0) {
+        n = n + 1;
+        p = p * (s->mu / (double)n);
+        cdf = cdf + p;
+    }
+    return n;
+}
+
+static double next_event_time_poisson(const or_scenario *s, uint64_t seed, uint32_t loc, double t_last) {
+    uint64_t k = (uint64_t)floor(t_last * s->inv_dt);
+    for (;;) {
+        const double start = (double)k * s->dt;
+        const uint32_t n = poisson_count(s, u53(interval_draw(seed, loc, k, 0)));
+        double best = INFINITY;
+        for (uint32_t i = 1; i <= n; ++i) {
+            const double t = start + u53(interval_draw(seed, loc, k, i)) * s->dt;
+            if (t > t_last && t < best) best = t;
+        }
+        if (best < INFINITY) return best;
+        k = k + 1;
+    }
+}
+
+/* Switches the scenario's event-time sampler (0 or 1, [hppp]); -1 if the   */
+/* sampler is unknown or lambda * dt > 700 for sampler 1.                    */
+OR_EXPORT int or_scenario_set_sampler(or_scenario *s, uint32_t sampler) {
+    if (sampler > 1) return -1;
+    const double mu = s->lambda * s->dt; /* exact: dt is a power of two */
+    if (sampler == 1 && !(mu <= 700.0)) return -1;
+    s->sampler = sampler;
+    s->mu = mu;
+    s->p0 = exp(-mu);
+    return 0;
+}
+
 OR_EXPORT double or_next_event_time(const or_scenario *s, uint64_t seed, uint32_t loc, double t_last) {
+    if (s->sampler == 1) return next_event_time_poisson(s, seed, loc, t_last);
     uint64_t k = (uint64_t)floor(t_last * s->inv_dt);
     for (;;) {
         double e = (double)k * s->dt;
