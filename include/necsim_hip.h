@@ -85,7 +85,19 @@ typedef struct {
 typedef struct {
     double lambda;
     double delta_t;
+    uint32_t sampler;  /* NH_SAMPLER_EXP (0, default) or NH_SAMPLER_POISSON (1) */
+    uint32_t reserved; /* set to zero */
 } nh_params;
+
+/* Event-time samplers (both give Exp(lambda) gaps; they draw different bits):
+ * NH_SAMPLER_EXP: from t_last, Exp(lambda) draws -log(U)/lambda summed from the
+ *   interval start (section "Exponential inter-event Times");
+ * NH_SAMPLER_POISSON: per interval a Poisson(lambda*delta_t) count, by a linear
+ *   search over its cdf from one uniform (appendix "Iterative Sampling"), of
+ *   events at start + U*delta_t; the next event is the smallest beyond t_last
+ *   (section "Homogeneous Poisson Point Process").  Needs lambda*delta_t <= 700. */
+#define NH_SAMPLER_EXP 0
+#define NH_SAMPLER_POISSON 1
 
 /* Tuning knobs; none of them changes any result.  Zero fields take defaults. */
 typedef struct {

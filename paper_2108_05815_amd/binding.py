@@ -37,7 +37,8 @@ class nh_dispersal(C.Structure):
 
 
 class nh_params(C.Structure):
-    _fields_ = [("lambda_", C.c_double), ("delta_t", C.c_double)]
+    _fields_ = [("lambda_", C.c_double), ("delta_t", C.c_double), ("sampler", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
 
 class nh_config(C.Structure):
@@ -179,7 +180,7 @@ class Scenario:
     """Device-resident scenario tables (nh_scenario_create)."""
 
     def __init__(self, capacity, weights, nu: float, *, mode: int = NH_DISPERSAL_SHARED, lam: float = 1.0,
-                 dt: float = 1.0):
+                 dt: float = 1.0, sampler: int = 0):
         cap = np.ascontiguousarray(capacity, dtype=np.uint32)
         if cap.ndim != 2:
             raise ValueError("capacity must be a 2-D (H, W) array")
@@ -188,17 +189,18 @@ class Scenario:
             raise ValueError("weights must be a square (2R+1, 2R+1) array")
         hab = nh_habitat(cap.shape[1], cap.shape[0], cap.ctypes.data_as(C.POINTER(C.c_uint32)))
         disp = nh_dispersal(w.shape[0] // 2, w.ctypes.data_as(C.POINTER(C.c_double)), mode)
-        par = nh_params(lam, dt)
+        par = nh_params(lam, dt, sampler, 0)
         h = C.c_void_p()
         _check(_lib.nh_scenario_create(C.byref(hab), C.byref(disp), nu, C.byref(par), C.byref(h)),
                "nh_scenario_create")
         self._h = h
-        self.nu, self.mode, self.lam, self.dt = nu, mode, lam, dt
+        self.nu, self.mode, self.lam, self.dt, self.sampler = nu, mode, lam, dt, sampler
         self.shape = cap.shape
 
     @classmethod
     def from_workload(cls, wl):
-        return cls(wl.capacity, wl.weights, wl.nu, mode=wl.mode, lam=wl.lam, dt=wl.dt)
+        return cls(wl.capacity, wl.weights, wl.nu, mode=wl.mode, lam=wl.lam, dt=wl.dt,
+                   sampler=getattr(wl, "sampler", 0))
 
     @property
     def handle(self):

@@ -102,6 +102,8 @@ struct JobDev {
     uint32_t *abund_counts_out;
     uint32_t *rich_counts;   // samples per slot of rich_set (abundance reporter)
     uint64_t rich_off;       // offset of rich_set in the run's species-set area
+    uint32_t sampler, sampler_pad; // NH_SAMPLER_EXP / NH_SAMPLER_POISSON
+    double mu, p0;                 // Poisson sampler: lambda * dt, exp(-lambda * dt)
 };
 
 // Per-job counters, written by the kernels.
@@ -162,7 +164,8 @@ struct JobView {
     const uint4 *table;
     const uint32_t *row_ptr;
     const uint32_t *cap;
-    uint32_t W, H, cmax, R, mode, n_shared, cap_const, caps_in_table;
+    uint32_t W, H, cmax, R, mode, n_shared, cap_const, caps_in_table, sampler;
+    double mu, p0;
 };
 
 // Op counters of one lane (summed per wave at the end of a kernel).
@@ -189,6 +192,9 @@ __device__ __forceinline__ JobView load_view(const JobDev *__restrict__ J) {
     v.n_shared = J->n_shared;
     v.cap_const = J->cap_const;
     v.caps_in_table = J->caps_in_table;
+    v.sampler = J->sampler;
+    v.mu = J->mu;
+    v.p0 = J->p0;
     return v;
 }
 
@@ -316,12 +322,73 @@ __device__ __forceinline__ double next_event_time_wide(const JobView &v, uint32_
     return -1.0;
 }
 
+// The Poisson sampler (section "Homogeneous Poisson Point Process"): the
+// events of interval k at loc are a Poisson(mu = lambda dt) count, from draw 0
+// of the interval's stream by a linear search over the Poisson cdf (p_0 =
+// exp(-mu), p_n = p_{n-1} mu / n, the first n whose cumulative sum reaches u;
+// also stop if p_n underflows), placed at k dt + U dt by draws 1 .. n.  The
+// next event after t_last is the smallest of them beyond it; an interval
+// without one moves the search to interval k+1.
+__device__ __forceinline__ double u53(uint64_t r) { return (double)(r >> 11) * 0x1.0p-53; }
+
+__device__ __forceinline__ uint32_t poisson_count(const JobView &v, double u) {
+    double p = v.p0, cdf = p;
+    uint32_t n = 0;
+    while (u > cdf && p > 0.0) {
+        n = n + 1;
+        p = p * (v.mu / (double)n);
+        cdf = cdf + p;
+    }
+    return n;
+}
+
+// Smallest event of interval k beyond t_last, or +inf; *draws and *blocks
+// receive what the interval consumed.
+__device__ __forceinline__ double poisson_interval(const JobView &v, uint32_t loc, uint64_t k, double t_last,
+                                                   uint32_t &draws, uint32_t &blocks) {
+    const double start = (double)k * v.dt;
+    uint32_t c0 = loc, c1 = (uint32_t)k, c2 = (uint32_t)(k >> 32), c3 = 0; // domain 0, call 0
+    philox10(c0, c1, c2, c3, v.key0, v.key1);
+    const uint32_t n = poisson_count(v, u53(((uint64_t)c1 << 32) | c0));
+    uint64_t second = ((uint64_t)c3 << 32) | c2;
+    double best = __builtin_inf();
+    for (uint32_t i = 1; i <= n; ++i) {
+        uint64_t r = second;
+        if ((i & 1u) == 0u) { // draw i opens call i / 2
+            uint32_t d0 = loc, d1 = (uint32_t)k, d2 = (uint32_t)(k >> 32), d3 = i >> 1;
+            philox10(d0, d1, d2, d3, v.key0, v.key1);
+            r = ((uint64_t)d1 << 32) | d0;
+            second = ((uint64_t)d3 << 32) | d2;
+        }
+        const double t = start + u53(r) * v.dt;
+        if (t > t_last && t < best) best = t;
+    }
+    draws = 1u + n;
+    blocks = (n >> 1) + 1u;
+    return best;
+}
+
+__device__ __forceinline__ double next_event_time_poisson(const JobView &v, uint32_t loc, double t_last,
+                                                          uint32_t *err, Counters &cnt) {
+    uint64_t k = (uint64_t)floor(t_last * v.inv_dt);
+    for (uint32_t guard = 0; guard < (1u << 24); ++guard, ++k) {
+        uint32_t draws, blocks;
+        const double e = poisson_interval(v, loc, k, t_last, draws, blocks);
+        cnt.draws += draws;
+        cnt.philox += blocks;
+        if (e < __builtin_inf()) return e;
+    }
+    atomicOr(err, kErrRunaway);
+    return -1.0;
+}
+
 // The same search for interval indices below 2^31 (every time below 2^31 dt):
 // the index is a u32, so its conversions are single instructions, and the
 // interval end is start + dt, which equals (k + 1) dt exactly because dt is a
 // power of two.  Bit-identical to next_event_time_wide.
 __device__ __forceinline__ double next_event_time(const JobView &v, uint32_t loc, double t_last, uint32_t *err,
                                                   Counters &cnt) {
+    if (v.sampler == NH_SAMPLER_POISSON) return next_event_time_poisson(v, loc, t_last, err, cnt);
     const double kf = floor(t_last * v.inv_dt);
     if (!(kf < 2147483648.0)) return next_event_time_wide(v, loc, t_last, err, cnt);
     uint32_t k = (uint32_t)kf;
@@ -578,6 +645,10 @@ __device__ __forceinline__ double half_mirror_f64(double x) {
 // Counters record what the one-lane search needs.
 __device__ __forceinline__ double next_event_time_group(const JobView &v, uint32_t loc, double t_last, uint32_t gl,
                                                         uint32_t grp_base, uint32_t *err, Counters &cnt) {
+    if (v.sampler == NH_SAMPLER_POISSON) { // every lane runs the one-lane search; lane 0 counts
+        Counters dummy;
+        return next_event_time_poisson(v, loc, t_last, err, gl == 0u ? cnt : dummy);
+    }
     const double kf = floor(t_last * v.inv_dt);
     if (__builtin_expect(!(kf < 2147483648.0), 0)) { // every lane runs the one-lane search; lane 0 counts
         Counters dummy;
@@ -712,8 +783,16 @@ __device__ __forceinline__ bool commit_event_group(const JobView &v, Pos &p, dou
 // its tag; counters match what the one-lane path records.
 constexpr uint32_t kStepOk = 0, kStepSpeciated = 1, kStepSlow = 2;
 
+// Sum over the 8 lanes of a group, in every lane: three DPP moves.
+__device__ __forceinline__ uint32_t group_sum8(uint32_t x) {
+    x += swap_neighbour(x);
+    x += (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E /* quad_perm [2,3,0,1] */, 0xF, 0xF, true);
+    return x + half_mirror(x);
+}
+
 template <bool kLds>
-__device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double &t, uint32_t gl, Counters &cnt) {
+__device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double &t, uint32_t gl, uint32_t grp_base,
+                                               Counters &cnt) {
     const uint64_t tb = (uint64_t)__double_as_longlong(t);
     const uint32_t call = gl & 1u;
     uint32_t a0 = p.loc, a1 = (uint32_t)tb, a2 = (uint32_t)(tb >> 32), a3 = (1u << 30) | call;
@@ -731,6 +810,26 @@ __device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double 
     const double kf = floor(t * v.inv_dt);
     const bool wide = !(kf < 2147483648.0);
     const uint32_t k = wide ? 0u : (uint32_t)kf;
+    if (v.sampler == NH_SAMPLER_POISSON) {
+        // Lane gl takes interval k + gl whole (every event of a later interval lies beyond t); the
+        // lowest interval with an event decides.  No event in k .. k+7 (or a wide index) is slow.
+        uint32_t draws_i, blocks_i;
+        const double best = poisson_interval(v, q.loc, (uint64_t)k + gl, t, draws_i, blocks_i);
+        const uint32_t hits = (uint32_t)((__ballot(best < __builtin_inf()) >> grp_base) & 0xFFu);
+        const bool slow = wide | (hits == 0u);
+        const uint32_t first = hits ? (uint32_t)(__ffs(hits) - 1) : 0u;
+        const double e = shfl_f64(best, (int)(grp_base + first));
+        const uint32_t sd = group_sum8(gl <= first ? draws_i : 0u), sb = group_sum8(gl <= first ? blocks_i : 0u);
+        const bool counted = (gl == 0u) & !spec & !slow;
+        cnt.philox += (gl == 0u ? 2u : 0u) + (counted ? sb : 0u);
+        cnt.draws += counted ? sd : 0u;
+        p.x = spec ? p.x : q.x;
+        p.y = spec ? p.y : q.y;
+        p.i = spec ? p.i : q.i;
+        p.loc = spec ? p.loc : q.loc;
+        t = (spec | slow) ? t : e;
+        return spec ? kStepSpeciated : (slow ? kStepSlow : kStepOk);
+    }
     const bool q0 = gl < 4u;
     const uint32_t kk = q0 ? k : k + (gl - 3u);
     uint32_t c0 = q.loc, c1 = kk, c2 = 0, c3 = q0 ? (gl >> 1) : 0u;
@@ -1237,7 +1336,7 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
                 uint32_t st;
                 do {
                     ++ev;
-                    st = group_step<kLds>(v, p, t, gl, cnt);
+                    st = group_step<kLds>(v, p, t, gl, grp_base, cnt);
                     if (__builtin_expect(st == kStepSlow, 0)) {
                         t = next_event_time_group(v, p.loc, t, gl, grp_base, err, cnt);
                         st = t < 0.0 ? kStepSlow : kStepOk; // kStepSlow now marks a runaway search
@@ -1627,6 +1726,8 @@ struct TableBuilder {
 
 struct nh_scenario {
     int device = 0;
+    uint32_t sampler = NH_SAMPLER_EXP;
+    double mu = 1.0, p0 = 0.0; // Poisson sampler: lambda * delta_t and exp(-lambda * delta_t)
     uint32_t W = 0, H = 0, R = 0, mode = 0, cmax = 0, cap_const = 0, n_shared = 0;
     uint64_t cells = 0, N = 0, n_entries = 0;
     double nu = 0, lambda = 1, dt = 1;
@@ -1840,6 +1941,10 @@ NH_API int nh_scenario_create(const nh_habitat *habitat, const nh_dispersal *dis
     if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(NH_EINVAL, "lambda must be positive and finite");
     if (!is_power_of_two(dt)) return fail(NH_EINVAL, "delta_t must be a positive power of two");
     if (lambda * dt > 1048576.0) return fail(NH_EINVAL, "lambda * delta_t must not exceed 2^20");
+    const uint32_t sampler = params ? params->sampler : NH_SAMPLER_EXP;
+    if (sampler > NH_SAMPLER_POISSON) return fail(NH_EINVAL, "unknown event-time sampler %u", sampler);
+    if (sampler == NH_SAMPLER_POISSON && !(lambda * dt <= 700.0))
+        return fail(NH_EINVAL, "the Poisson sampler needs lambda * delta_t <= 700");
     const uint32_t side = 2 * R + 1;
     for (uint32_t k = 0; k < side * side; ++k) {
         const double w = dispersal->h_weights[k];
@@ -1878,6 +1983,9 @@ NH_API int nh_scenario_create(const nh_habitat *habitat, const nh_dispersal *dis
     s->nu = nu;
     s->lambda = lambda;
     s->dt = dt;
+    s->sampler = sampler;
+    s->mu = lambda * dt; // exact: delta_t is a power of two
+    s->p0 = std::exp(-s->mu);
     s->nu_thresh = u53_threshold(nu);
 
     TableBuilder tb;
@@ -2095,6 +2203,9 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
         d.n_shared = s->n_shared;
         d.cap_const = s->cap_const;
         d.caps_in_table = (s->mode == NH_DISPERSAL_PER_DEME && s->cmax <= 0xFFFFu) ? 1u : 0u;
+        d.sampler = s->sampler;
+        d.mu = s->mu;
+        d.p0 = s->p0;
         d.lin_base = (uint32_t)base;
         d.n = (uint32_t)jobs[j].n;
         d.start_round = 0;
@@ -2539,6 +2650,9 @@ void job_descriptor(JobDev &d, const nh_job &job, unsigned long long *rich_set, 
     d.n_shared = sc->n_shared;
     d.cap_const = sc->cap_const;
     d.caps_in_table = (sc->mode == NH_DISPERSAL_PER_DEME && sc->cmax <= 0xFFFFu) ? 1u : 0u;
+    d.sampler = sc->sampler;
+    d.mu = sc->mu;
+    d.p0 = sc->p0;
     d.lin_base = (uint32_t)lin_base;
     d.n = (uint32_t)job.n;
     d.start_round = 0;

@@ -40,6 +40,7 @@ class Workload:
     lam: float = 1.0
     dt: float = 1.0
     meta: dict = field(default_factory=dict)
+    sampler: int = 0              # 0: exponential sums, 1: Poisson count per interval
 
     @property
     def individuals(self) -> int:

@@ -436,6 +436,72 @@ def test_reporters_match_the_oracle_and_the_species(B, torch_mod):
         B.batch_run([(scns[0], 1, ss[0], outs[0], None, bad)], ws)
 
 
+def _poisson(w):
+    import copy
+    x = copy.copy(w)
+    x.sampler = 1
+    if x.samples is None:
+        x.samples = np.arange(int(x.capacity.astype(np.uint64).sum()), dtype=np.uint64)
+    return x
+
+
+POISSON = [_poisson(SMALL[k]) for k in (0, 2, 3, 5, 8)] + [
+    _poisson(W.spatial_torus(24, 2, 1.5, 4, 0.02, [5], name="torus 24 lambda 4 dt 0.5")),
+    _poisson(W.nonspatial(400, 0.05, [9], name="nonspatial J=400 lambda 0.25 dt 8"))]
+POISSON[-2].lam, POISSON[-2].dt = 4.0, 0.5
+POISSON[-1].lam, POISSON[-1].dt = 0.25, 8.0
+
+
+@pytest.mark.parametrize("wl", POISSON, ids=[w.name for w in POISSON])
+def test_poisson_sampler_bitexact(B, torch_mod, wl):
+    """The Poisson-count event-time sampler: GPU == oracle for the plain entry point and for both
+    lane layouts forced, with the speciation events of the reporters equal to the oracle's."""
+    torch = torch_mod
+    dev = torch.device("cuda:0")
+    osc = oracle.Scenario(wl.capacity, wl.weights, wl.nu, mode=wl.mode, lam=wl.lam, dt=wl.dt, sampler=1)
+    ref, _, _ = osc.simulate_culled(wl.seeds[0], wl.samples, 2.0)
+    scn = B.Scenario.from_workload(wl)
+    got, rich, _ = B.simulate(scn, wl.seeds[0], wl.samples)
+    assert np.array_equal(got, ref) and rich == oracle.richness(ref)
+    n = len(wl.samples)
+    s = torch.from_numpy(wl.samples.astype(np.int64)).to(dev)
+    ws = torch.empty(B.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
+    for coop in (1 << 30, 1):
+        out = torch.empty(n, dtype=torch.int64, device=dev)
+        r1 = torch.zeros(1, dtype=torch.int64, device=dev)
+        rep = _reporters(torch, n, dev)
+        B.batch_run([(scn, wl.seeds[0], s, out, r1, rep)], ws, B.make_config(coop_max=coop))
+        got = out.cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, ref), coop
+        check_reporters(got, int(r1.item()), rep, wl.seeds[0], osc if n <= 2000 else None, wl.samples)
+
+
+def test_poisson_sampler_torus_full_and_mixed_batch(B, torch_mod):
+    """The 256x256 torus under the Poisson sampler, bit-exact; a batch mixing both samplers equals
+    each job alone."""
+    torch = torch_mod
+    dev = torch.device("cuda:0")
+    wl = _poisson(W.config2())
+    osc = oracle.Scenario(wl.capacity, wl.weights, wl.nu, sampler=1)
+    ref, _, _ = osc.simulate_culled(42, wl.samples, 16.0)
+    scn_p = B.Scenario.from_workload(wl)
+    got, _, _ = B.simulate(scn_p, 42, wl.samples)
+    assert np.array_equal(got, ref)
+    wl_e = W.config2()
+    scn_e = B.Scenario.from_workload(wl_e)
+    n = len(wl.samples)
+    s = torch.from_numpy(wl.samples.astype(np.int64)).to(dev)
+    outs = [torch.empty(n, dtype=torch.int64, device=dev) for _ in range(4)]
+    jobs = [(scn_p, 42, s, outs[0], None), (scn_e, 42, s, outs[1], None), (scn_p, 43, s, outs[2], None),
+            (scn_e, 43, s, outs[3], None)]
+    ws = torch.empty(B.workspace_bytes(4 * n, 4), dtype=torch.uint8, device=dev)
+    B.batch_run(jobs, ws, B.make_config(solo_max=64))
+    assert np.array_equal(outs[0].cpu().numpy().view(np.uint64), ref)
+    for k, (scn, seed) in enumerate([(scn_p, 42), (scn_e, 42), (scn_p, 43), (scn_e, 43)]):
+        alone, _, _ = B.simulate(scn, seed, wl.samples)
+        assert np.array_equal(outs[k].cpu().numpy().view(np.uint64), alone), k
+
+
 def test_batch_with_empty_and_duplicate_jobs_and_device_entry_point(B, torch_mod):
     """Empty jobs inside a batch, the same job twice, and nh_simulate_device agree with the plain form."""
     import ctypes as C
