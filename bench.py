@@ -213,6 +213,7 @@ def main():
         host_s = time.perf_counter() - t0
         line["host_buffers"] = {"entry": "nh_simulate", "runs": 5, "ms_per_run": host_s * 200.0,
                                 "events_per_s": host_ev / host_s}
+        line["poisson_sampler"] = sampler_form(B, W, torch, cfg, stream)
         line["batched"] = batched_form(args, B, W, torch)
         line["serve"] = served_form(args, W, torch)
     if args.c3:
@@ -220,6 +221,31 @@ def main():
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def sampler_form(B, W, torch, cfg, stream, steps: int = 10) -> dict:
+    """The same torus with the Poisson-count event-time sampler (other bits, same law), timed like
+    the headline runs: the comparison the paper makes between its two samplers."""
+    import copy
+    dev = torch.device("cuda:0")
+    wl = copy.copy(W.config2())
+    wl.sampler = 1
+    scn = B.Scenario.from_workload(wl)
+    n = len(wl.samples)
+    samples = torch.from_numpy(wl.samples.astype(np.int64)).to(dev)
+    out = torch.empty(n, dtype=torch.int64, device=dev)
+    ws = torch.empty(B.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
+    for k in range(2):
+        B.batch_run([(scn, 1000 + k, samples, out, None)], ws, cfg, stream)
+    torch.cuda.synchronize()
+    ev = 0
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev += B.batch_run([(scn, 42 + k, samples, out, None)], ws, cfg, stream)[0]["events"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"workload": wl.name + ", Poisson-count sampler", "steps": steps, "ms_per_step": el * 1e3 / steps,
+            "events_per_s": ev / el, "individuals_per_s": steps * n / el}
 
 
 def habitat_form(B, W, torch) -> dict:
