@@ -342,17 +342,27 @@ __device__ __forceinline__ uint32_t poisson_count(const JobView &v, double u) {
     return n;
 }
 
-// Smallest event of interval k beyond t_last, or +inf; *draws and *blocks
-// receive what the interval consumed.
+// Smallest event of interval k beyond t_last, or +inf; draws and blocks
+// receive what the interval consumes in the definition (draw 0 and points
+// 1 .. n, two draws per Philox call).  The first two calls are evaluated side
+// by side, so counts up to 3 need no further call in sequence.
 __device__ __forceinline__ double poisson_interval(const JobView &v, uint32_t loc, uint64_t k, double t_last,
                                                    uint32_t &draws, uint32_t &blocks) {
     const double start = (double)k * v.dt;
-    uint32_t c0 = loc, c1 = (uint32_t)k, c2 = (uint32_t)(k >> 32), c3 = 0; // domain 0, call 0
-    philox10(c0, c1, c2, c3, v.key0, v.key1);
-    const uint32_t n = poisson_count(v, u53(((uint64_t)c1 << 32) | c0));
-    uint64_t second = ((uint64_t)c3 << 32) | c2;
+    uint32_t a0 = loc, a1 = (uint32_t)k, a2 = (uint32_t)(k >> 32), a3 = 0; // domain 0, call 0
+    uint32_t b0 = loc, b1 = (uint32_t)k, b2 = (uint32_t)(k >> 32), b3 = 1; // call 1
+    philox10(a0, a1, a2, a3, v.key0, v.key1);
+    philox10(b0, b1, b2, b3, v.key0, v.key1);
+    const uint32_t n = poisson_count(v, u53(((uint64_t)a1 << 32) | a0));
+    const double t1 = start + u53(((uint64_t)a3 << 32) | a2) * v.dt;
+    const double t2 = start + u53(((uint64_t)b1 << 32) | b0) * v.dt;
+    const double t3 = start + u53(((uint64_t)b3 << 32) | b2) * v.dt;
     double best = __builtin_inf();
-    for (uint32_t i = 1; i <= n; ++i) {
+    best = (n >= 1u && t1 > t_last) ? t1 : best;
+    best = (n >= 2u && t2 > t_last && t2 < best) ? t2 : best;
+    best = (n >= 3u && t3 > t_last && t3 < best) ? t3 : best;
+    uint64_t second = 0;
+    for (uint32_t i = 4; i <= n; ++i) { // rare: more than three events in the interval
         uint64_t r = second;
         if ((i & 1u) == 0u) { // draw i opens call i / 2
             uint32_t d0 = loc, d1 = (uint32_t)k, d2 = (uint32_t)(k >> 32), d3 = i >> 1;
