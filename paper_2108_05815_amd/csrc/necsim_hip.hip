@@ -6,22 +6,29 @@
 // Independence" unless noted):
 //   "Environmental RNG Priming"         - counter-based hash keyed on (seed, location, time)
 //   "Aligning the RNGs of Colliding Individuals" and "Exponential inter-event
-//   Times" (memoryless sums)            - next_event_time()
-//   "Summary of the Independent Algorithm" - commit_event() and the lane loop
+//   Times" (memoryless sums)            - next_event_time(), next_event_time_group(), group_step()
+//   "Homogeneous Poisson Point Process" and appendix "Iterative Sampling"
+//                                       - the Poisson-count sampler (poisson_interval())
+//   "Summary of the Independent Algorithm" - commit_event(), disperse(), species_of(), the lane loops
 //   implementation chapter, "Deduplicating Redundant Individuals" and the
-//   Water-Level algorithm               - horizon rounds + (location, next time) hash cull
+//   Water-Level algorithm               - horizon rounds + (job, location, next time) hash cull
 //   appendix "Sampling Probability Distributions" - 53-bit uniforms, inverse-transform Exp
 //   related work "Counter-based Pseudo-Random Number Generators" - Philox4x32-10
 //
-// Layout: one lane per lineage.  Lineage state is structure-of-arrays in HBM
-// (loc u32, next-event time f64, parent u32, species u64, job u32, events u32),
-// touched once per lineage per round; everything inside a round lives in
-// registers.  The round kernel is persistent over a fixed grid: lanes refill
-// from a device work queue with one wave-aggregated atomic, finished lineages
-// are either retired (speciation), merged (hash hit on (job, loc, t_next)) or
-// compacted into the next round's queue with ballot + mbcnt + one atomic per
-// wave.  Round kernels are replayed from captured HIP graphs while the host
-// polls a host-mapped status word written by the last workgroup of each round.
+// Layout: lineage state is structure-of-arrays in HBM (loc u32 and next-event
+// time f64 double-buffered by round parity, parent u32, species u64, job u32,
+// events u32, speciation event), touched once per lineage per round;
+// everything inside a round lives in registers.  A round kernel runs a fixed
+// grid over the round's queue: waves reserve chunks of it with one atomic and
+// hand items to idle lanes; each lineage runs one lane (long queues) or 8
+// lanes (short queues, and the solo queue of nearly finished jobs in runs of
+// several jobs) until its next event lies beyond its job's horizon; a lineage
+// whose (job, location, next time) another lineage already holds is merged at
+// pickup; survivors are staged per wave in LDS and appended to the next queue.
+// A one-thread epilogue publishes survivors and job completions to
+// host-mapped memory.  Round kernels are replayed from captured HIP graphs
+// while the host polls that status word.  Between rounds the workspace is a
+// complete checkpoint (suspend and resume).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -755,29 +762,6 @@ __device__ __forceinline__ double next_event_time_group(const JobView &v, uint32
 // Swap a 32-bit value with the neighbouring lane (lane ^ 1): one DPP move.
 __device__ __forceinline__ uint32_t swap_neighbour(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1 /* quad_perm [1,0,3,2] */, 0xF, 0xF, true);
-}
-
-// One event for a group: even lanes evaluate event block 0 and odd lanes
-// event block 1 side by side and swap words with their neighbour, so every
-// lane holds r0..r3.  Every lane then applies the same speciation test and
-// dispersal, so the group stays in agreement without further exchange.
-template <bool kLds = false>
-__device__ __forceinline__ bool commit_event_group(const JobView &v, Pos &p, double t, uint32_t gl, Counters &cnt) {
-    const uint64_t tb = (uint64_t)__double_as_longlong(t);
-    const uint32_t tlo = (uint32_t)tb, thi = (uint32_t)(tb >> 32);
-    const uint32_t call = gl & 1u;
-    uint32_t a0 = p.loc, a1 = tlo, a2 = thi, a3 = (1u << 30) | call;
-    philox10(a0, a1, a2, a3, v.key0, v.key1);
-    const uint32_t b0 = swap_neighbour(a0), b1 = swap_neighbour(a1), b2 = swap_neighbour(a2),
-                   b3 = swap_neighbour(a3);
-    const uint64_t wa = ((uint64_t)a1 << 32) | a0, wb = ((uint64_t)a3 << 32) | a2; // my block
-    const uint64_t xa = ((uint64_t)b1 << 32) | b0, xb = ((uint64_t)b3 << 32) | b2; // neighbour's block
-    const uint64_t r0 = call ? xa : wa, r1 = call ? xb : wb;
-    const uint64_t r2 = call ? wa : xa, r3 = call ? wb : xb;
-    if (gl == 0) cnt.philox += 2;
-    if (__builtin_expect((r0 >> 11) < v.nu_thresh, 0)) return true;
-    disperse<kLds>(v, p, r1, r2, r3);
-    return false;
 }
 
 // One event of a group plus the first pass of the following event-time
