@@ -67,6 +67,9 @@ def _load():
         lib.or_scenario_table.restype = C.c_uint32
         lib.or_sample_location.argtypes = [C.c_void_p, C.c_uint64]
         lib.or_sample_location.restype = C.c_uint32
+        lib.or_scenario_create_implicit.argtypes = [C.c_uint32, C.c_uint32, C.c_double, C.c_double, C.c_double,
+                                                    C.c_double, C.POINTER(C.c_void_p)]
+        lib.or_scenario_create_implicit.restype = C.c_int
         lib.or_scenario_set_sampler.argtypes = [C.c_void_p, C.c_uint32]
         lib.or_scenario_set_sampler.restype = C.c_int
         lib.or_next_event_time.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_double]
@@ -160,6 +163,24 @@ class Scenario:
         self.sampler = sampler
         if sampler and lib.or_scenario_set_sampler(h, sampler) != 0:
             raise ValueError("invalid event-time sampler")
+
+    @classmethod
+    def implicit(cls, J: int, J_meta: int, m: float, nu_meta: float, *, lam: float = 1.0, dt: float = 1.0,
+                 sampler: int = 0):
+        """The spatially implicit scenario: local community J (sample ids 0..J-1) with migration
+        probability m per event into a dynamic metacommunity of J_meta with speciation nu_meta."""
+        self = cls.__new__(cls)
+        lib = _load()
+        h = C.c_void_p()
+        if lib.or_scenario_create_implicit(J, J_meta, m, nu_meta, lam, dt, C.byref(h)) != 0:
+            raise ValueError("invalid spatially implicit scenario")
+        self._h, self._lib = h, lib
+        self.H, self.W, self.R = 1, 2, 0
+        self.nu, self.mode, self.lam, self.dt, self.sampler = nu_meta, 2, lam, dt, sampler
+        self._cap, self._w = np.array([[J, J_meta]], np.uint32), np.ones((1, 1))
+        if sampler and lib.or_scenario_set_sampler(h, sampler) != 0:
+            raise ValueError("invalid event-time sampler")
+        return self
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -26,6 +26,11 @@
  *           algorithm (time-aligned rounds);
  *   [comp]  section "The Statically Checked Component System" (habitat,
  *           dispersal sampler, coalescence sampler = uniform deme index);
+ *   [impl]  background section "Spatially Implicit" and its appendix (a local
+ *           community of J with per-event migration probability m into a
+ *           non-spatial metacommunity of J_m with speciation nu_m; no
+ *           speciation in the local community; the metacommunity simulated
+ *           alongside, i.e. dynamic and finite);
  *   [hppp]  section "Homogeneous Poisson Point Process" of the Independent
  *           Algorithm chapter (the log-free alternative to the exponential
  *           sums: a Poisson count per interval, the events uniform in it) and
@@ -206,7 +211,8 @@ typedef struct {
 } or_table;
 
 typedef struct {
-    uint32_t W, H, R, mode;
+    uint32_t W, H, R, mode; /* mode 0 shared table, 1 per-deme tables, 2 spatially implicit [impl] */
+    double mig;             /* mode 2: migration probability of a local event */
     uint32_t *cap;
     uint64_t *prefix; /* prefix[c] = sum of cap before cell c; prefix[W H] = N */
     uint32_t cmax;
@@ -333,6 +339,23 @@ OR_EXPORT int or_scenario_create(uint32_t W, uint32_t H, const uint32_t *cap, ui
     return 0;
 }
 
+/* [impl] The spatially implicit scenario: two communities, the local one of J
+ * individuals (cell 0, sample ids 0 .. J-1) and the metacommunity of J_m
+ * (cell 1, ids J .. J+J_m-1).  0 < m <= 1 (with m = 0 a local lineage could
+ * never speciate) and 0 < nu_m <= 1. */
+OR_EXPORT int or_scenario_create_implicit(uint32_t J, uint32_t J_meta, double m, double nu_meta, double lambda,
+                                          double dt, or_scenario **out) {
+    *out = NULL;
+    if (J == 0 || J_meta == 0 || !(m > 0.0 && m <= 1.0)) return -1;
+    const uint32_t cap[2] = {J, J_meta};
+    const double w = 1.0;
+    int rc = or_scenario_create(2, 1, cap, 0, &w, 0, nu_meta, lambda, dt, out);
+    if (rc != 0) return rc;
+    (*out)->mode = 2;
+    (*out)->mig = m;
+    return 0;
+}
+
 OR_EXPORT uint64_t or_scenario_individuals(const or_scenario *s) { return s->prefix[(uint64_t)s->W * s->H]; }
 
 static const or_table *table_for(or_scenario *s, uint32_t cell) {
@@ -455,6 +478,24 @@ static int commit_event(or_scenario *s, uint64_t seed, uint32_t *loc, double t, 
     uint64_t r0, r1, r2, r3;
     uint64_t tb = f64_bits(t);
     hash_block(seed, *loc, tb, DOM_EVENT, 0, &r0, &r1);
+    if (s->mode == 2) {
+        /* [impl] cell 0 is the local community, cell 1 the metacommunity: only the latter
+         * speciates (r0); a local event migrates with probability m (r1); the deme index
+         * is uniform over the target community (r3). */
+        const uint32_t cell = *loc / s->cmax;
+        if (cell == 1 && u53(r0) < s->nu) {
+            uint64_t a, b;
+            hash_block(seed, *loc, tb, DOM_SPECIES, 0, &a, &b);
+            *species = a;
+            return 1;
+        }
+        hash_block(seed, *loc, tb, DOM_EVENT, 1, &r2, &r3);
+        const uint32_t target = (cell == 0 && u53(r1) < s->mig) ? 1u : cell;
+        *loc = target * s->cmax + mulhi64_u32(r3, s->cap[target]);
+        if (dx_out) *dx_out = 0;
+        if (dy_out) *dy_out = 0;
+        return 0;
+    }
     if (u53(r0) < s->nu) {
         uint64_t a, b;
         hash_block(seed, *loc, tb, DOM_SPECIES, 0, &a, &b);

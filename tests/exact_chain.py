@@ -70,6 +70,24 @@ def dispersal_law(capacity: np.ndarray, weights: np.ndarray, mode: int) -> np.nd
 def expected_richness(capacity: np.ndarray, weights: np.ndarray, mode: int, nu: float, start_slots) -> float:
     """E[S] for the set of initially occupied slots (indices into slots_of(capacity))."""
     D = dispersal_law(capacity, weights, mode)
+    return expected_richness_law(D, np.full(D.shape[0], nu), start_slots)
+
+
+def implicit_law(J: int, J_meta: int, m: float) -> tuple[np.ndarray, list]:
+    """Slot-level law of the spatially implicit model (background section "Spatially Implicit"):
+    slots 0..J-1 are the local community, J..J+J_meta-1 the metacommunity.  A local lineage's
+    parent is a uniform metacommunity slot with probability m, else a uniform local slot; a
+    metacommunity lineage's parent is a uniform metacommunity slot."""
+    n = J + J_meta
+    D = np.zeros((n, n))
+    D[:J, :J] = (1.0 - m) / J
+    D[:J, J:] = m / J_meta
+    D[J:, J:] = 1.0 / J_meta
+    return D, list(range(J))
+
+
+def expected_richness_law(D: np.ndarray, nu_slot: np.ndarray, start_slots) -> float:
+    """E[S] for a slot-level dispersal law D and a per-slot speciation probability."""
     n = D.shape[0]
     start = frozenset(start_slots)
     m_max = len(start)
@@ -82,6 +100,7 @@ def expected_richness(capacity: np.ndarray, weights: np.ndarray, mode: int, nu: 
         for A, row in pos.items():
             for a in A:
                 rest = A - {a}
+                nu = nu_slot[a]
                 rhs[row] += nu * (1.0 + S[rest]) / m
                 for b in range(n):
                     p = D[a, b]
