@@ -180,6 +180,19 @@ typedef struct {
 int nh_scenario_create(const nh_habitat *habitat, const nh_dispersal *dispersal, double nu, const nh_params *params,
                        nh_scenario **out);
 
+/* The spatially implicit scenario (background section "Spatially Implicit" and
+ * its appendix): a local community of J individuals (cell 0; sample ids
+ * 0 .. J-1) that never speciates and whose lineages migrate, with probability
+ * m per event, into a non-spatial metacommunity of J_meta individuals (cell 1;
+ * ids J .. J+J_meta-1) simulated alongside (finite and dynamic), which
+ * speciates with probability nu_meta.  Within a community the parent's deme
+ * index is uniform (event draw r3); the migration coin is draw r1 (U < m);
+ * speciation is tested on r0 in the metacommunity only.  params as for
+ * nh_scenario_create.  NH_EINVAL for J or J_meta = 0, m outside (0, 1] (with
+ * m = 0 a local lineage would never speciate) or nu_meta outside (0, 1]. */
+int nh_scenario_create_implicit(uint32_t J, uint32_t J_meta, double m, double nu_meta, const nh_params *params,
+                                nh_scenario **out);
+
 void nh_scenario_destroy(nh_scenario *scenario);
 
 /* Number of individuals N (sum of capacities). */

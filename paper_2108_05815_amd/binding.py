@@ -82,6 +82,9 @@ class nh_completion(C.Structure):
 _lib.nh_scenario_create.argtypes = [C.POINTER(nh_habitat), C.POINTER(nh_dispersal), C.c_double,
                                     C.POINTER(nh_params), C.POINTER(C.c_void_p)]
 _lib.nh_scenario_create.restype = C.c_int
+_lib.nh_scenario_create_implicit.argtypes = [C.c_uint32, C.c_uint32, C.c_double, C.c_double, C.POINTER(nh_params),
+                                             C.POINTER(C.c_void_p)]
+_lib.nh_scenario_create_implicit.restype = C.c_int
 _lib.nh_scenario_destroy.argtypes = [C.c_void_p]
 _lib.nh_scenario_destroy.restype = None
 _lib.nh_scenario_individuals.argtypes = [C.c_void_p]
@@ -129,6 +132,7 @@ _lib.nh_measure_gather.restype = C.c_int
 # The C names, for callers that want the raw ABI.
 nh_scenario_create = _lib.nh_scenario_create
 nh_scenario_destroy = _lib.nh_scenario_destroy
+nh_scenario_create_implicit = _lib.nh_scenario_create_implicit
 nh_scenario_individuals = _lib.nh_scenario_individuals
 nh_scenario_table_bytes = _lib.nh_scenario_table_bytes
 nh_workspace_bytes = _lib.nh_workspace_bytes
@@ -149,7 +153,7 @@ nh_server_poll = _lib.nh_server_poll
 nh_server_drain = _lib.nh_server_drain
 nh_server_destroy = _lib.nh_server_destroy
 
-EXPORTED = ["nh_scenario_create", "nh_scenario_destroy", "nh_scenario_individuals", "nh_scenario_table_bytes",
+EXPORTED = ["nh_scenario_create", "nh_scenario_create_implicit", "nh_scenario_destroy", "nh_scenario_individuals", "nh_scenario_table_bytes",
             "nh_workspace_bytes", "nh_scenario_footprint_bytes", "nh_batch_run", "nh_batch_resume",
             "nh_simulate_device",
             "nh_simulate", "nh_last_error", "nh_version", "nh_server_bytes", "nh_server_create",
@@ -196,6 +200,21 @@ class Scenario:
         self._h = h
         self.nu, self.mode, self.lam, self.dt, self.sampler = nu, mode, lam, dt, sampler
         self.shape = cap.shape
+
+    @classmethod
+    def implicit(cls, J: int, J_meta: int, m: float, nu_meta: float, *, lam: float = 1.0, dt: float = 1.0,
+                 sampler: int = 0):
+        """nh_scenario_create_implicit: local community J (sample ids 0..J-1) with migration
+        probability m into a dynamic metacommunity of J_meta with speciation nu_meta."""
+        self = cls.__new__(cls)
+        h = C.c_void_p()
+        par = nh_params(lam, dt, sampler, 0)
+        _check(_lib.nh_scenario_create_implicit(J, J_meta, m, nu_meta, C.byref(par), C.byref(h)),
+               "nh_scenario_create_implicit")
+        self._h = h
+        self.nu, self.mode, self.lam, self.dt, self.sampler = nu_meta, 2, lam, dt, sampler
+        self.shape = (1, 2)
+        return self
 
     @classmethod
     def from_workload(cls, wl):

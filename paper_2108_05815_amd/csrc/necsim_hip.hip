@@ -72,6 +72,7 @@ int fail(int code, const char *fmt, ...) {
                         __FILE__, __LINE__);                                                  \
     } while (0)
 
+constexpr uint32_t kModeImplicit = 2u; // scenario mode set by nh_scenario_create_implicit
 constexpr uint32_t kErrBadSample = 1u;
 constexpr uint32_t kJobSentinelSpecies = 1u; // JobState.flags: a species id equal to the set's empty marker
 constexpr uint32_t kJobBadSample = 2u;       // JobState.flags: a sample id was not below N
@@ -111,6 +112,7 @@ struct JobDev {
     uint64_t rich_off;       // offset of rich_set in the run's species-set area
     uint32_t sampler, sampler_pad; // NH_SAMPLER_EXP / NH_SAMPLER_POISSON
     double mu, p0;                 // Poisson sampler: lambda * dt, exp(-lambda * dt)
+    uint64_t mig_thresh;           // spatially implicit: a local event migrates iff (r1 >> 11) < mig_thresh
 };
 
 // Per-job counters, written by the kernels.
@@ -173,6 +175,8 @@ struct JobView {
     const uint32_t *cap;
     uint32_t W, H, cmax, R, mode, n_shared, cap_const, caps_in_table, sampler;
     double mu, p0;
+    uint64_t mig_thresh;
+    uint32_t cap_local, cap_meta; // spatially implicit: the two communities' sizes
 };
 
 // Op counters of one lane (summed per wave at the end of a kernel).
@@ -202,6 +206,11 @@ __device__ __forceinline__ JobView load_view(const JobDev *__restrict__ J) {
     v.sampler = J->sampler;
     v.mu = J->mu;
     v.p0 = J->p0;
+    v.mig_thresh = J->mig_thresh;
+    if (J->mode == kModeImplicit) {
+        v.cap_local = J->cap[0];
+        v.cap_meta = J->cap[1];
+    }
     return v;
 }
 
@@ -457,6 +466,14 @@ __device__ __forceinline__ Pos pos_from_loc(const JobView &v, uint32_t loc) {
     return p;
 }
 
+// Speciation threshold at the lineage's position: nu everywhere, except in
+// the local community of a spatially implicit scenario, which never speciates.
+template <bool kLds>
+__device__ __forceinline__ uint64_t speciation_threshold(const JobView &v, const Pos &p) {
+    if (kLds) return v.nu_thresh; // an LDS-staged table means the shared mode
+    return (v.mode == kModeImplicit && p.x == 0u) ? 0ull : v.nu_thresh;
+}
+
 // Species id of a lineage that speciates at (loc, t): the species domain of
 // the hash, keyed like the event draws.
 __device__ __forceinline__ uint64_t species_of(const JobView &v, uint32_t loc, double t) {
@@ -471,6 +488,16 @@ __device__ __forceinline__ uint64_t species_of(const JobView &v, uint32_t loc, d
 // A table staged in LDS is always the shared one.
 template <bool kLds>
 __device__ __forceinline__ void disperse(const JobView &v, Pos &p, uint64_t r1, uint64_t r2, uint64_t r3) {
+    if (!kLds && v.mode == kModeImplicit) {
+        // Spatially implicit (background section "Spatially Implicit"): cell 0 is the local
+        // community, cell 1 the metacommunity; a local event migrates with probability m (r1),
+        // and the deme index is uniform over the target community (r3).
+        const uint32_t target = (p.x == 0u && (r1 >> 11) < v.mig_thresh) ? 1u : p.x;
+        p.x = target;
+        p.i = mulhi_index(r3, target ? v.cap_meta : v.cap_local);
+        p.loc = target * v.cmax + p.i;
+        return;
+    }
     uint32_t first, n;
     if (kLds || v.mode == NH_DISPERSAL_SHARED) {
         first = 0;
@@ -519,7 +546,7 @@ __device__ __forceinline__ bool commit_event(const JobView &v, Pos &p, double t,
     const uint64_t r2 = ((uint64_t)b1 << 32) | b0;
     const uint64_t r3 = ((uint64_t)b3 << 32) | b2;
     cnt.philox += 2;
-    if (__builtin_expect((r0 >> 11) < v.nu_thresh, 0)) return true;
+    if (__builtin_expect((r0 >> 11) < speciation_threshold<kLds>(v, p), 0)) return true;
     disperse<kLds>(v, p, r1, r2, r3);
     return false;
 }
@@ -797,7 +824,7 @@ __device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double 
     const uint64_t xa = ((uint64_t)b1 << 32) | b0, xb = ((uint64_t)b3 << 32) | b2;
     const uint64_t r0 = call ? xa : wa, r1 = call ? xb : wb;
     const uint64_t r2 = call ? wa : xa, r3 = call ? wb : xb;
-    const bool spec = (r0 >> 11) < v.nu_thresh;
+    const bool spec = (r0 >> 11) < speciation_threshold<kLds>(v, p);
     Pos q = p;
     disperse<kLds>(v, q, r1, r2, r3);
 
@@ -1722,6 +1749,7 @@ struct nh_scenario {
     int device = 0;
     uint32_t sampler = NH_SAMPLER_EXP;
     double mu = 1.0, p0 = 0.0; // Poisson sampler: lambda * delta_t and exp(-lambda * delta_t)
+    uint64_t mig_thresh = 0;   // spatially implicit scenario: ceil(m 2^53)
     uint32_t W = 0, H = 0, R = 0, mode = 0, cmax = 0, cap_const = 0, n_shared = 0;
     uint64_t cells = 0, N = 0, n_entries = 0;
     double nu = 0, lambda = 1, dt = 1;
@@ -2087,6 +2115,23 @@ NH_API int nh_scenario_create(const nh_habitat *habitat, const nh_dispersal *dis
     return NH_OK;
 }
 
+NH_API int nh_scenario_create_implicit(uint32_t J, uint32_t J_meta, double m, double nu_meta,
+                                       const nh_params *params, nh_scenario **out) {
+    if (!out) return fail(NH_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (J == 0 || J_meta == 0) return fail(NH_EINVAL, "both communities need individuals");
+    if (!(m > 0.0 && m <= 1.0)) return fail(NH_EINVAL, "the migration probability must lie in (0, 1]");
+    const uint32_t cap[2] = {J, J_meta};
+    const double w = 1.0;
+    const nh_habitat hab{2, 1, cap};
+    const nh_dispersal disp{0, &w, NH_DISPERSAL_SHARED};
+    if (int rc = nh_scenario_create(&hab, &disp, nu_meta, params, out)) return rc;
+    (*out)->mode = kModeImplicit;
+    (*out)->cap_const = 0;
+    (*out)->mig_thresh = u53_threshold(m);
+    return NH_OK;
+}
+
 NH_API void nh_scenario_destroy(nh_scenario *s) { scenario_free(s); }
 
 NH_API uint64_t nh_scenario_individuals(const nh_scenario *s) { return s ? s->N : 0; }
@@ -2200,6 +2245,7 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
         d.sampler = s->sampler;
         d.mu = s->mu;
         d.p0 = s->p0;
+        d.mig_thresh = s->mig_thresh;
         d.lin_base = (uint32_t)base;
         d.n = (uint32_t)jobs[j].n;
         d.start_round = 0;
@@ -2647,6 +2693,7 @@ void job_descriptor(JobDev &d, const nh_job &job, unsigned long long *rich_set, 
     d.sampler = sc->sampler;
     d.mu = sc->mu;
     d.p0 = sc->p0;
+    d.mig_thresh = sc->mig_thresh;
     d.lin_base = (uint32_t)lin_base;
     d.n = (uint32_t)job.n;
     d.start_round = 0;

@@ -502,6 +502,51 @@ def test_poisson_sampler_torus_full_and_mixed_batch(B, torch_mod):
         assert np.array_equal(outs[k].cpu().numpy().view(np.uint64), alone), k
 
 
+IMPLICIT = [(3, 4, 0.3, 0.2, 0), (50, 400, 0.1, 0.01, 0), (1000, 20000, 0.02, 1e-3, 0), (200, 200, 1.0, 0.05, 0),
+            (300, 3000, 0.05, 0.005, 1)]
+
+
+@pytest.mark.parametrize("J,Jm,m,nu,sampler", IMPLICIT, ids=[f"J{c[0]}_Jm{c[1]}_m{c[2]}_s{c[4]}" for c in IMPLICIT])
+def test_spatially_implicit_bitexact(B, torch_mod, J, Jm, m, nu, sampler):
+    """The spatially implicit scenario: GPU == oracle for the local community's samples (and one
+    run that also samples the metacommunity), both lane layouts, with the reporters."""
+    torch = torch_mod
+    dev = torch.device("cuda:0")
+    osc = oracle.Scenario.implicit(J, Jm, m, nu, sampler=sampler)
+    scn = B.Scenario.implicit(J, Jm, m, nu, sampler=sampler)
+    for samples in (np.arange(J, dtype=np.uint64), np.arange(0, J + Jm, max(1, (J + Jm) // 500), dtype=np.uint64)):
+        ref, _, _ = osc.simulate_culled(11, samples, 4.0)
+        got, rich, _ = B.simulate(scn, 11, samples)
+        assert np.array_equal(got, ref) and rich == oracle.richness(ref)
+    samples = np.arange(J, dtype=np.uint64)
+    ref, _, _ = osc.simulate_culled(11, samples, 4.0)
+    s = torch.from_numpy(samples.astype(np.int64)).to(dev)
+    ws = torch.empty(B.workspace_bytes(J, 1), dtype=torch.uint8, device=dev)
+    for coop in (1 << 30, 1):
+        out = torch.empty(J, dtype=torch.int64, device=dev)
+        r1 = torch.zeros(1, dtype=torch.int64, device=dev)
+        rep = _reporters(torch, J, dev)
+        B.batch_run([(scn, 11, s, out, r1, rep)], ws, B.make_config(coop_max=coop))
+        got = out.cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, ref), coop
+        check_reporters(got, int(r1.item()), rep, 11, osc if J <= 300 else None, samples)
+
+
+def test_spatially_implicit_in_a_mixed_batch(B, torch_mod):
+    torch = torch_mod
+    dev = torch.device("cuda:0")
+    scns = [B.Scenario.implicit(400, 5000, 0.05, 2e-3), B.Scenario.from_workload(SMALL[2]),
+            B.Scenario.implicit(100, 100, 0.5, 0.02, sampler=1), B.Scenario.from_workload(SMALL[0])]
+    ns = [400, SMALL[2].individuals, 100, SMALL[0].individuals]
+    ss = [torch.arange(n, dtype=torch.int64, device=dev) for n in ns]
+    outs = [torch.empty(n, dtype=torch.int64, device=dev) for n in ns]
+    ws = torch.empty(B.workspace_bytes(sum(ns), 4), dtype=torch.uint8, device=dev)
+    B.batch_run([(scns[k], 5 + k, ss[k], outs[k], None) for k in range(4)], ws, B.make_config(solo_max=32))
+    for k in range(4):
+        alone, _, _ = B.simulate(scns[k], 5 + k, np.arange(ns[k], dtype=np.uint64))
+        assert np.array_equal(outs[k].cpu().numpy().view(np.uint64), alone), k
+
+
 def test_batch_with_empty_and_duplicate_jobs_and_device_entry_point(B, torch_mod):
     """Empty jobs inside a batch, the same job twice, and nh_simulate_device agree with the plain form."""
     import ctypes as C

@@ -98,3 +98,10 @@ def test_isolated_deme_in_per_deme_mode_is_rejected(B):
 def test_resume_rejects_bad_calls_before_touching_the_gpu(B):
     assert B.nh_batch_resume(None, 0, None, 0, None, None, None) == B.NH_EINVAL
     assert B.nh_batch_resume(None, 1, None, 0, None, None, None) == B.NH_EINVAL
+
+
+@pytest.mark.parametrize("J,Jm,m,nu", [(0, 10, 0.5, 0.1), (10, 0, 0.5, 0.1), (10, 10, 0.0, 0.1), (10, 10, 1.5, 0.1),
+                                       (10, 10, 0.5, 0.0), (10, 10, float("nan"), 0.1)])
+def test_implicit_scenario_validation(B, J, Jm, m, nu):
+    h = C.c_void_p()
+    assert B.nh_scenario_create_implicit(J, Jm, m, nu, None, C.byref(h)) == B.NH_EINVAL
