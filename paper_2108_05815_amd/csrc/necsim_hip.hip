@@ -255,15 +255,6 @@ __device__ __forceinline__ uint32_t mulhi_index(uint64_t r, uint32_t n) {
 // split into a 32-bit head and a tail.  Every floating-point operation is
 // spelled out (no contraction), so the result is the same bits on any
 // IEEE-754 binary64 machine that evaluates the same sequence.
-// IEEE fused multiply-add d = a*b + c in the three-address encoding: with the
-// two-address form the compiler copies each loop-invariant coefficient into the
-// accumulator first (one extra move per Horner step).
-__device__ __forceinline__ double fma3(double a, double b, double c) {
-    double d;
-    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-    return d;
-}
-
 __device__ __forceinline__ double log_u53o(uint64_t r) {
     const uint64_t q = (r >> 11) + 1ull;          // 1 .. 2^53
     const int nb = 64 - __clzll((long long)q);     // bit length, 1 .. 54
@@ -281,15 +272,15 @@ __device__ __forceinline__ double log_u53o(uint64_t r) {
     const double s = f / (2.0 + f);
     const double z = s * s;
     double p = 1.0 / 21.0;
-    p = fma3(p, z, 1.0 / 19.0);
-    p = fma3(p, z, 1.0 / 17.0);
-    p = fma3(p, z, 1.0 / 15.0);
-    p = fma3(p, z, 1.0 / 13.0);
-    p = fma3(p, z, 1.0 / 11.0);
-    p = fma3(p, z, 1.0 / 9.0);
-    p = fma3(p, z, 1.0 / 7.0);
-    p = fma3(p, z, 1.0 / 5.0);
-    p = fma3(p, z, 1.0 / 3.0);
+    p = __builtin_fma(p, z, 1.0 / 19.0);
+    p = __builtin_fma(p, z, 1.0 / 17.0);
+    p = __builtin_fma(p, z, 1.0 / 15.0);
+    p = __builtin_fma(p, z, 1.0 / 13.0);
+    p = __builtin_fma(p, z, 1.0 / 11.0);
+    p = __builtin_fma(p, z, 1.0 / 9.0);
+    p = __builtin_fma(p, z, 1.0 / 7.0);
+    p = __builtin_fma(p, z, 1.0 / 5.0);
+    p = __builtin_fma(p, z, 1.0 / 3.0);
     p = p * z;
     const double two_s = s + s;
     const double log_m = __builtin_fma(two_s, p, two_s);
