@@ -72,6 +72,8 @@ def _load():
         lib.or_scenario_create_implicit.restype = C.c_int
         lib.or_scenario_set_sampler.argtypes = [C.c_void_p, C.c_uint32]
         lib.or_scenario_set_sampler.restype = C.c_int
+        lib.or_scenario_set_protracted.argtypes = [C.c_void_p, C.c_double]
+        lib.or_scenario_set_protracted.restype = C.c_int
         lib.or_next_event_time.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_double]
         lib.or_next_event_time.restype = C.c_double
         lib.or_simulate_naive.argtypes = [C.c_void_p, C.c_uint64, u64p, C.c_uint64, u64p, f64p, u64p]
@@ -140,7 +142,7 @@ class Scenario:
     capacity (zero-capacity targets dropped)."""
 
     def __init__(self, capacity, weights, nu: float, *, mode: int = 0, lam: float = 1.0, dt: float = 1.0,
-                 sampler: int = 0):
+                 sampler: int = 0, tau: float = 0.0):
         lib = _load()
         cap = np.ascontiguousarray(capacity, dtype=np.uint32)
         if cap.ndim != 2:
@@ -163,10 +165,18 @@ class Scenario:
         self.sampler = sampler
         if sampler and lib.or_scenario_set_sampler(h, sampler) != 0:
             raise ValueError("invalid event-time sampler")
+        self._set_tau(tau)
+
+    def _set_tau(self, tau: float):
+        """Protracted speciation (appendix "Protracted Speciation"): speciation draws at events
+        fewer than tau generations (lambda * t < tau) before the present are ignored."""
+        self.tau = tau
+        if tau and self._lib.or_scenario_set_protracted(self._h, tau) != 0:
+            raise ValueError("invalid protracted speciation tau")
 
     @classmethod
     def implicit(cls, J: int, J_meta: int, m: float, nu_meta: float, *, lam: float = 1.0, dt: float = 1.0,
-                 sampler: int = 0):
+                 sampler: int = 0, tau: float = 0.0):
         """The spatially implicit scenario: local community J (sample ids 0..J-1) with migration
         probability m per event into a dynamic metacommunity of J_meta with speciation nu_meta."""
         self = cls.__new__(cls)
@@ -180,6 +190,7 @@ class Scenario:
         self._cap, self._w = np.array([[J, J_meta]], np.uint32), np.ones((1, 1))
         if sampler and lib.or_scenario_set_sampler(h, sampler) != 0:
             raise ValueError("invalid event-time sampler")
+        self._set_tau(tau)
         return self
 
     def __del__(self):

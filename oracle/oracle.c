@@ -35,7 +35,10 @@
  *           Algorithm chapter (the log-free alternative to the exponential
  *           sums: a Poisson count per interval, the events uniform in it) and
  *           appendix "Iterative Sampling: Geometric and Poisson" (the count by
- *           a linear search over the Poisson cdf, one uniform per count).
+ *           a linear search over the Poisson cdf, one uniform per count);
+ *   [prot]  appendix "Protracted Speciation" (a speciation completes only
+ *           after tau generations, so the draws at events younger than tau
+ *           are ignored).
  */
 #include <math.h>
 #include <stdint.h>
@@ -220,6 +223,7 @@ typedef struct {
     double nu, lambda, inv_lambda, dt, inv_dt;
     uint32_t sampler; /* 0: exponential sums; 1: Poisson count + uniform points [hppp] */
     double mu, p0;    /* sampler 1: lambda * dt and exp(-lambda * dt) */
+    double tau;       /* protracted speciation: generations; 0 is point speciation [prot] */
     or_table shared;  /* mode 0 */
     or_table **cells; /* mode 1, built on first visit */
 } or_scenario;
@@ -452,6 +456,22 @@ OR_EXPORT int or_scenario_set_sampler(or_scenario *s, uint32_t sampler) {
     return 0;
 }
 
+/* [prot] Protracted speciation: a speciation takes tau generations to    */
+/* complete, so a speciation draw at an event less than tau generations     */
+/* before the present is ignored and that event is an ordinary dispersal.  */
+/* A generation is one mean lifetime, 1/lambda time units, so an event at   */
+/* time t is lambda * t generations old.  -1 unless tau is finite, >= 0.    */
+OR_EXPORT int or_scenario_set_protracted(or_scenario *s, double tau) {
+    if (!(tau >= 0.0) || isinf(tau)) return -1;
+    s->tau = tau;
+    return 0;
+}
+
+/* Whether a speciation draw at time t counts ([prot]). */
+static int speciation_counts(const or_scenario *s, double t) {
+    return !(s->lambda * t < s->tau);
+}
+
 OR_EXPORT double or_next_event_time(const or_scenario *s, uint64_t seed, uint32_t loc, double t_last) {
     if (s->sampler == 1) return next_event_time_poisson(s, seed, loc, t_last);
     uint64_t k = (uint64_t)floor(t_last * s->inv_dt);
@@ -469,8 +489,9 @@ OR_EXPORT double or_next_event_time(const or_scenario *s, uint64_t seed, uint32_
 }
 
 /* [ind] Summary: at the event (loc, t) prime on (loc, t); speciate iff      */
-/* U(r0) < nu; otherwise disperse: alias column from r1, alias coin from r2, */
-/* torus offset, then a uniform deme index from r3 ([comp] coalescence       */
+/* U(r0) < nu (and the event is at least tau generations old, [prot]); else */
+/* disperse: alias column from r1, alias coin from r2, the torus offset,    */
+/* then a uniform deme index from r3 ([comp] coalescence       */
 /* sampler).  Returns 1 on speciation (species id in *species), else 0 and   */
 /* the new location in *loc.                                                  */
 static int commit_event(or_scenario *s, uint64_t seed, uint32_t *loc, double t, uint64_t *species,
@@ -483,7 +504,7 @@ static int commit_event(or_scenario *s, uint64_t seed, uint32_t *loc, double t, 
          * speciates (r0); a local event migrates with probability m (r1); the deme index
          * is uniform over the target community (r3). */
         const uint32_t cell = *loc / s->cmax;
-        if (cell == 1 && u53(r0) < s->nu) {
+        if (cell == 1 && speciation_counts(s, t) && u53(r0) < s->nu) {
             uint64_t a, b;
             hash_block(seed, *loc, tb, DOM_SPECIES, 0, &a, &b);
             *species = a;
@@ -496,7 +517,7 @@ static int commit_event(or_scenario *s, uint64_t seed, uint32_t *loc, double t, 
         if (dy_out) *dy_out = 0;
         return 0;
     }
-    if (u53(r0) < s->nu) {
+    if (speciation_counts(s, t) && u53(r0) < s->nu) {
         uint64_t a, b;
         hash_block(seed, *loc, tb, DOM_SPECIES, 0, &a, &b);
         *species = a;

@@ -86,11 +86,10 @@ def implicit_law(J: int, J_meta: int, m: float) -> tuple[np.ndarray, list]:
     return D, list(range(J))
 
 
-def expected_richness_law(D: np.ndarray, nu_slot: np.ndarray, start_slots) -> float:
-    """E[S] for a slot-level dispersal law D and a per-slot speciation probability."""
+def richness_table(D: np.ndarray, nu_slot: np.ndarray, m_max: int) -> dict:
+    """E[S] for every occupied set of at most m_max slots, under a slot-level dispersal law D and a
+    per-slot speciation probability."""
     n = D.shape[0]
-    start = frozenset(start_slots)
-    m_max = len(start)
     S = {frozenset(): 0.0}
     for m in range(1, m_max + 1):
         level = [frozenset(c) for c in combinations(range(n), m)]
@@ -116,7 +115,42 @@ def expected_richness_law(D: np.ndarray, nu_slot: np.ndarray, start_slots) -> fl
         sol = np.linalg.solve(M, rhs)
         for A, k in pos.items():
             S[A] = float(sol[k])
-    return S[start]
+    return S
+
+
+def expected_richness_law(D: np.ndarray, nu_slot: np.ndarray, start_slots) -> float:
+    """E[S] for a slot-level dispersal law D and a per-slot speciation probability."""
+    start = frozenset(start_slots)
+    return richness_table(D, nu_slot, len(start))[start]
+
+
+def protracted_expected_richness_law(D: np.ndarray, nu_slot: np.ndarray, tau: float, start_slots) -> float:
+    """E[S] under protracted speciation (appendix "Protracted Speciation"): for the first tau
+    generations back from the present no speciation counts, so the occupied set evolves by
+    dispersal and coalescence alone, each lineage moving once per generation on average (a
+    continuous-time chain over occupied sets, solved with a matrix exponential); from tau on,
+    the point-speciation chain above takes over from whichever set is occupied then (the events
+    are memoryless, so the two phases join at tau)."""
+    from scipy.linalg import expm
+
+    n = D.shape[0]
+    start = frozenset(start_slots)
+    sets = [frozenset(c) for m in range(1, len(start) + 1) for c in combinations(range(n), m)]
+    pos = {A: k for k, A in enumerate(sets)}
+    Q = np.zeros((len(sets), len(sets)))
+    for A, row in pos.items():
+        for a in A:
+            rest = A - {a}
+            for b in range(n):
+                p = D[a, b]
+                if p == 0.0 or b == a:
+                    continue
+                to = rest if b in rest else rest | {b}
+                Q[row, pos[to]] += p
+                Q[row, row] -= p
+    P = expm(Q * tau)[pos[start]]
+    S = richness_table(D, nu_slot, len(start))
+    return float(sum(P[k] * S[A] for A, k in pos.items()))
 
 
 def ewens_mean(J: int, nu: float) -> float:
