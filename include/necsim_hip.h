@@ -81,12 +81,19 @@ typedef struct {
 
 /* Scenario constants that change the random draws (never tuned):
  * lambda > 0 is the per-individual turnover rate, delta_t the repriming
- * interval, a positive power of two with lambda*delta_t <= 2^20. */
+ * interval, a positive power of two with lambda*delta_t <= 2^20.
+ * tau >= 0 selects protracted speciation (appendix "Protracted Speciation"):
+ * a speciation completes only tau generations (tau / lambda time units) after
+ * it happens, so the speciation draw of an event at time t with lambda*t < tau
+ * (binary64 product) is ignored and that event disperses like any other; tau = 0
+ * is point speciation.  tau / lambda must lie below 2^60 (NH_EINVAL otherwise).
+ * A zero-filled struct is not valid: lambda and delta_t have no zero default. */
 typedef struct {
     double lambda;
     double delta_t;
     uint32_t sampler;  /* NH_SAMPLER_EXP (0, default) or NH_SAMPLER_POISSON (1) */
     uint32_t reserved; /* set to zero */
+    double tau;        /* protracted speciation, generations; 0 for point speciation */
 } nh_params;
 
 /* Event-time samplers (both give Exp(lambda) gaps; they draw different bits):

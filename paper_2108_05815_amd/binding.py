@@ -38,7 +38,7 @@ class nh_dispersal(C.Structure):
 
 class nh_params(C.Structure):
     _fields_ = [("lambda_", C.c_double), ("delta_t", C.c_double), ("sampler", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("reserved", C.c_uint32), ("tau", C.c_double)]
 
 
 class nh_config(C.Structure):
@@ -184,7 +184,9 @@ class Scenario:
     """Device-resident scenario tables (nh_scenario_create)."""
 
     def __init__(self, capacity, weights, nu: float, *, mode: int = NH_DISPERSAL_SHARED, lam: float = 1.0,
-                 dt: float = 1.0, sampler: int = 0):
+                 dt: float = 1.0, sampler: int = 0, tau: float = 0.0):
+        """tau > 0: protracted speciation (speciation draws at events fewer than tau generations,
+        lambda * t < tau, before the present are ignored and those events disperse)."""
         cap = np.ascontiguousarray(capacity, dtype=np.uint32)
         if cap.ndim != 2:
             raise ValueError("capacity must be a 2-D (H, W) array")
@@ -193,33 +195,33 @@ class Scenario:
             raise ValueError("weights must be a square (2R+1, 2R+1) array")
         hab = nh_habitat(cap.shape[1], cap.shape[0], cap.ctypes.data_as(C.POINTER(C.c_uint32)))
         disp = nh_dispersal(w.shape[0] // 2, w.ctypes.data_as(C.POINTER(C.c_double)), mode)
-        par = nh_params(lam, dt, sampler, 0)
+        par = nh_params(lam, dt, sampler, 0, tau)
         h = C.c_void_p()
         _check(_lib.nh_scenario_create(C.byref(hab), C.byref(disp), nu, C.byref(par), C.byref(h)),
                "nh_scenario_create")
         self._h = h
-        self.nu, self.mode, self.lam, self.dt, self.sampler = nu, mode, lam, dt, sampler
+        self.nu, self.mode, self.lam, self.dt, self.sampler, self.tau = nu, mode, lam, dt, sampler, tau
         self.shape = cap.shape
 
     @classmethod
     def implicit(cls, J: int, J_meta: int, m: float, nu_meta: float, *, lam: float = 1.0, dt: float = 1.0,
-                 sampler: int = 0):
+                 sampler: int = 0, tau: float = 0.0):
         """nh_scenario_create_implicit: local community J (sample ids 0..J-1) with migration
         probability m into a dynamic metacommunity of J_meta with speciation nu_meta."""
         self = cls.__new__(cls)
         h = C.c_void_p()
-        par = nh_params(lam, dt, sampler, 0)
+        par = nh_params(lam, dt, sampler, 0, tau)
         _check(_lib.nh_scenario_create_implicit(J, J_meta, m, nu_meta, C.byref(par), C.byref(h)),
                "nh_scenario_create_implicit")
         self._h = h
-        self.nu, self.mode, self.lam, self.dt, self.sampler = nu_meta, 2, lam, dt, sampler
+        self.nu, self.mode, self.lam, self.dt, self.sampler, self.tau = nu_meta, 2, lam, dt, sampler, tau
         self.shape = (1, 2)
         return self
 
     @classmethod
     def from_workload(cls, wl):
         return cls(wl.capacity, wl.weights, wl.nu, mode=wl.mode, lam=wl.lam, dt=wl.dt,
-                   sampler=getattr(wl, "sampler", 0))
+                   sampler=getattr(wl, "sampler", 0), tau=getattr(wl, "tau", 0.0))
 
     @property
     def handle(self):

@@ -113,6 +113,7 @@ struct JobDev {
     uint32_t sampler, sampler_pad; // NH_SAMPLER_EXP / NH_SAMPLER_POISSON
     double mu, p0;                 // Poisson sampler: lambda * dt, exp(-lambda * dt)
     uint64_t mig_thresh;           // spatially implicit: a local event migrates iff (r1 >> 11) < mig_thresh
+    double tau_t;                  // protracted speciation: no speciation at events with t < tau_t
 };
 
 // Per-job counters, written by the kernels.
@@ -177,6 +178,7 @@ struct JobView {
     double mu, p0;
     uint64_t mig_thresh;
     uint32_t cap_local, cap_meta; // spatially implicit: the two communities' sizes
+    double tau_t;                 // protracted speciation threshold time
 };
 
 // Op counters of one lane (summed per wave at the end of a kernel).
@@ -207,6 +209,7 @@ __device__ __forceinline__ JobView load_view(const JobDev *__restrict__ J) {
     v.mu = J->mu;
     v.p0 = J->p0;
     v.mig_thresh = J->mig_thresh;
+    v.tau_t = J->tau_t;
     if (J->mode == kModeImplicit) {
         v.cap_local = J->cap[0];
         v.cap_meta = J->cap[1];
@@ -457,12 +460,18 @@ __device__ __forceinline__ Pos pos_from_loc(const JobView &v, uint32_t loc) {
     return p;
 }
 
-// Speciation threshold at the lineage's position: nu everywhere, except in
-// the local community of a spatially implicit scenario, which never speciates.
+// Speciation threshold of the event at (p, t): nu, except in the local community
+// of a spatially implicit scenario, which never speciates, and at events younger
+// than the protracted-speciation time (appendix "Protracted Speciation": a
+// speciation completes only tau generations after it happens, so going back
+// from the present the draws of the first tau generations are ignored and the
+// event disperses).  tau_t is the smallest time with lambda * tau_t >= tau in
+// binary64, so t < tau_t exactly when lambda * t < tau.
 template <bool kLds>
-__device__ __forceinline__ uint64_t speciation_threshold(const JobView &v, const Pos &p) {
-    if (kLds) return v.nu_thresh; // an LDS-staged table means the shared mode
-    return (v.mode == kModeImplicit && p.x == 0u) ? 0ull : v.nu_thresh;
+__device__ __forceinline__ uint64_t speciation_threshold(const JobView &v, const Pos &p, double t) {
+    const bool young = t < v.tau_t;
+    if (kLds) return young ? 0ull : v.nu_thresh; // an LDS-staged table means the shared mode
+    return (young | (v.mode == kModeImplicit && p.x == 0u)) ? 0ull : v.nu_thresh;
 }
 
 // Species id of a lineage that speciates at (loc, t): the species domain of
@@ -537,7 +546,7 @@ __device__ __forceinline__ bool commit_event(const JobView &v, Pos &p, double t,
     const uint64_t r2 = ((uint64_t)b1 << 32) | b0;
     const uint64_t r3 = ((uint64_t)b3 << 32) | b2;
     cnt.philox += 2;
-    if (__builtin_expect((r0 >> 11) < speciation_threshold<kLds>(v, p), 0)) return true;
+    if (__builtin_expect((r0 >> 11) < speciation_threshold<kLds>(v, p, t), 0)) return true;
     disperse<kLds>(v, p, r1, r2, r3);
     return false;
 }
@@ -815,7 +824,7 @@ __device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double 
     const uint64_t xa = ((uint64_t)b1 << 32) | b0, xb = ((uint64_t)b3 << 32) | b2;
     const uint64_t r0 = call ? xa : wa, r1 = call ? xb : wb;
     const uint64_t r2 = call ? wa : xa, r3 = call ? wb : xb;
-    const bool spec = (r0 >> 11) < speciation_threshold<kLds>(v, p);
+    const bool spec = (r0 >> 11) < speciation_threshold<kLds>(v, p, t);
     Pos q = p;
     disperse<kLds>(v, q, r1, r2, r3);
 
@@ -1628,6 +1637,21 @@ inline uint64_t pow2_at_least(uint64_t x, uint64_t floor_value) {
 // (r >> 11) < ceil(p 2^53)  <=>  (r >> 11) * 2^-53 < p.
 inline uint64_t u53_threshold(double p) { return (uint64_t)std::ceil(std::ldexp(p, 53)); }
 
+// Smallest binary64 t >= 0 with lambda * t >= tau after rounding.  The rounded
+// product is non-decreasing in t, so lambda * t < tau holds exactly for t below
+// it: the protracted-speciation test needs one compare per event and no product.
+double protracted_threshold(double tau, double lambda) {
+    if (!(tau > 0.0)) return 0.0;
+    double t = tau / lambda;
+    while (lambda * t < tau) t = std::nextafter(t, INFINITY);
+    while (t > 0.0) {
+        const double below = std::nextafter(t, 0.0);
+        if (lambda * below < tau) break;
+        t = below;
+    }
+    return t;
+}
+
 bool is_power_of_two(double x) {
     int e;
     const double m = std::frexp(x, &e);
@@ -1741,6 +1765,7 @@ struct nh_scenario {
     uint32_t sampler = NH_SAMPLER_EXP;
     double mu = 1.0, p0 = 0.0; // Poisson sampler: lambda * delta_t and exp(-lambda * delta_t)
     uint64_t mig_thresh = 0;   // spatially implicit scenario: ceil(m 2^53)
+    double tau = 0, tau_t = 0; // protracted speciation: generations, and the threshold time
     uint32_t W = 0, H = 0, R = 0, mode = 0, cmax = 0, cap_const = 0, n_shared = 0;
     uint64_t cells = 0, N = 0, n_entries = 0;
     double nu = 0, lambda = 1, dt = 1;
@@ -1958,6 +1983,9 @@ NH_API int nh_scenario_create(const nh_habitat *habitat, const nh_dispersal *dis
     if (sampler > NH_SAMPLER_POISSON) return fail(NH_EINVAL, "unknown event-time sampler %u", sampler);
     if (sampler == NH_SAMPLER_POISSON && !(lambda * dt <= 700.0))
         return fail(NH_EINVAL, "the Poisson sampler needs lambda * delta_t <= 700");
+    const double tau = params ? params->tau : 0.0;
+    if (!(tau >= 0.0) || !(tau / lambda < 0x1p60))
+        return fail(NH_EINVAL, "tau must be non-negative with tau / lambda below 2^60");
     const uint32_t side = 2 * R + 1;
     for (uint32_t k = 0; k < side * side; ++k) {
         const double w = dispersal->h_weights[k];
@@ -2000,6 +2028,8 @@ NH_API int nh_scenario_create(const nh_habitat *habitat, const nh_dispersal *dis
     s->mu = lambda * dt; // exact: delta_t is a power of two
     s->p0 = std::exp(-s->mu);
     s->nu_thresh = u53_threshold(nu);
+    s->tau = tau;
+    s->tau_t = protracted_threshold(tau, lambda);
 
     TableBuilder tb;
     tb.W = W;
@@ -2237,6 +2267,7 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
         d.mu = s->mu;
         d.p0 = s->p0;
         d.mig_thresh = s->mig_thresh;
+        d.tau_t = s->tau_t;
         d.lin_base = (uint32_t)base;
         d.n = (uint32_t)jobs[j].n;
         d.start_round = 0;
@@ -2685,6 +2716,7 @@ void job_descriptor(JobDev &d, const nh_job &job, unsigned long long *rich_set, 
     d.mu = sc->mu;
     d.p0 = sc->p0;
     d.mig_thresh = sc->mig_thresh;
+    d.tau_t = sc->tau_t;
     d.lin_base = (uint32_t)lin_base;
     d.n = (uint32_t)job.n;
     d.start_round = 0;

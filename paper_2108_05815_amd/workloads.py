@@ -41,6 +41,7 @@ class Workload:
     dt: float = 1.0
     meta: dict = field(default_factory=dict)
     sampler: int = 0              # 0: exponential sums, 1: Poisson count per interval
+    tau: float = 0.0              # protracted speciation (generations); 0: point speciation
 
     @property
     def individuals(self) -> int:

@@ -547,6 +547,88 @@ def test_spatially_implicit_in_a_mixed_batch(B, torch_mod):
         assert np.array_equal(outs[k].cpu().numpy().view(np.uint64), alone), k
 
 
+def _protracted(w, tau, lam=None, dt=None, sampler=0):
+    import copy
+    x = copy.copy(w)
+    x.tau, x.sampler = tau, sampler
+    x.lam = x.lam if lam is None else lam
+    x.dt = x.dt if dt is None else dt
+    x.name = f"{w.name} tau={tau} lambda={x.lam} dt={x.dt} sampler={sampler}"
+    if x.samples is None:
+        x.samples = np.arange(int(x.capacity.astype(np.uint64).sum()), dtype=np.uint64)
+    return x
+
+
+# lambda = 0.3 is not a power of two, so tau / lambda is inexact and the threshold time the
+# library derives must still decide exactly as lambda * t < tau does
+PROTRACTED = [_protracted(SMALL[0], 10.0), _protracted(SMALL[2], 5.0), _protracted(SMALL[3], 40.0, lam=0.3),
+              _protracted(SMALL[4], 3.0, lam=0.3), _protracted(SMALL[5], 25.0, sampler=1),
+              _protracted(SMALL[2], 2.5, lam=4.0, dt=0.5, sampler=1), _protracted(SMALL[8], 1.0)]
+
+
+@pytest.mark.parametrize("wl", PROTRACTED, ids=[w.name for w in PROTRACTED])
+def test_protracted_speciation_bitexact(B, torch_mod, wl):
+    """Protracted speciation: GPU == oracle for the plain entry point and both lane layouts, with
+    every reported speciation at least tau generations old and equal to the oracle's event."""
+    torch = torch_mod
+    dev = torch.device("cuda:0")
+    say(wl.name, "n =", len(wl.samples))
+    osc = oracle.Scenario(wl.capacity, wl.weights, wl.nu, mode=wl.mode, lam=wl.lam, dt=wl.dt,
+                          sampler=wl.sampler, tau=wl.tau)
+    ref, _, _ = osc.simulate_culled(wl.seeds[0], wl.samples, 2.0)
+    scn = B.Scenario.from_workload(wl)
+    got, rich, _ = B.simulate(scn, wl.seeds[0], wl.samples)
+    assert np.array_equal(got, ref) and rich == oracle.richness(ref)
+    n = len(wl.samples)
+    s = torch.from_numpy(wl.samples.astype(np.int64)).to(dev)
+    ws = torch.empty(B.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
+    for coop in (1 << 30, 1):
+        out = torch.empty(n, dtype=torch.int64, device=dev)
+        r1 = torch.zeros(1, dtype=torch.int64, device=dev)
+        rep = _reporters(torch, n, dev)
+        B.batch_run([(scn, wl.seeds[0], s, out, r1, rep)], ws, B.make_config(coop_max=coop))
+        got = out.cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, ref), coop
+        check_reporters(got, int(r1.item()), rep, wl.seeds[0], osc if n <= 2000 else None, wl.samples)
+        assert (wl.lam * rep["spec_time"].cpu().numpy() >= wl.tau).all()
+
+
+def test_protracted_speciation_torus_full_implicit_and_mixed_batch(B, torch_mod):
+    """The 256x256 torus with tau = 20 generations, bit-exact; the spatially implicit scenario with
+    tau; a batch mixing point and protracted speciation equals each job alone."""
+    torch = torch_mod
+    dev = torch.device("cuda:0")
+    wl = _protracted(W.config2(), 20.0)
+    say(wl.name)
+    osc = oracle.Scenario(wl.capacity, wl.weights, wl.nu, tau=20.0)
+    ref, _, _ = osc.simulate_culled(42, wl.samples, 16.0)
+    scn_p = B.Scenario.from_workload(wl)
+    got, rich_p, _ = B.simulate(scn_p, 42, wl.samples)
+    assert np.array_equal(got, ref)
+    scn_e = B.Scenario.from_workload(W.config2())
+    _, rich_e, _ = B.simulate(scn_e, 42, wl.samples)
+    assert rich_p < rich_e  # young species no longer count
+    J, Jm = 300, 3000
+    oimp = oracle.Scenario.implicit(J, Jm, 0.05, 0.005, tau=4.0)
+    gimp = B.Scenario.implicit(J, Jm, 0.05, 0.005, tau=4.0)
+    samples = np.arange(J, dtype=np.uint64)
+    assert np.array_equal(B.simulate(gimp, 11, samples)[0], oimp.simulate_culled(11, samples, 4.0)[0])
+    n = len(wl.samples)
+    s = torch.from_numpy(wl.samples.astype(np.int64)).to(dev)
+    si = torch.from_numpy(samples.astype(np.int64)).to(dev)
+    outs = [torch.empty(n, dtype=torch.int64, device=dev) for _ in range(3)] + [
+        torch.empty(J, dtype=torch.int64, device=dev)]
+    jobs = [(scn_p, 42, s, outs[0], None), (scn_e, 42, s, outs[1], None), (scn_p, 43, s, outs[2], None),
+            (gimp, 11, si, outs[3], None)]
+    ws = torch.empty(B.workspace_bytes(3 * n + J, 4), dtype=torch.uint8, device=dev)
+    B.batch_run(jobs, ws, B.make_config(solo_max=64))
+    assert np.array_equal(outs[0].cpu().numpy().view(np.uint64), ref)
+    for k, (scn, seed, smp) in enumerate([(scn_p, 42, wl.samples), (scn_e, 42, wl.samples),
+                                          (scn_p, 43, wl.samples), (gimp, 11, samples)]):
+        alone, _, _ = B.simulate(scn, seed, smp)
+        assert np.array_equal(outs[k].cpu().numpy().view(np.uint64), alone), k
+
+
 def test_batch_with_empty_and_duplicate_jobs_and_device_entry_point(B, torch_mod):
     """Empty jobs inside a batch, the same job twice, and nh_simulate_device agree with the plain form."""
     import ctypes as C

@@ -55,6 +55,10 @@ def test_workspace_sizes_grow_with_the_batch(B):
     (dict(lam=0.0), "lambda"),
     (dict(lam=float("inf")), "lambda"),
     (dict(lam=4096.0, dt=512.0), "2^20"),
+    (dict(tau=-1.0), "tau"),
+    (dict(tau=float("nan")), "tau"),
+    (dict(tau=float("inf")), "tau"),
+    (dict(tau=2.0 ** 58, lam=0.125), "tau"),
 ])
 def test_scenario_parameter_validation(B, kwargs, msg):
     nu = kwargs.pop("nu", 0.1)
