@@ -74,6 +74,12 @@ def _load():
         lib.or_scenario_set_sampler.restype = C.c_int
         lib.or_scenario_set_protracted.argtypes = [C.c_void_p, C.c_double]
         lib.or_scenario_set_protracted.restype = C.c_int
+        lib.or_event_stream.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64), C.c_uint64, C.c_uint64,
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_uint32),
+                                        C.POINTER(C.c_uint32), C.c_uint64, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
+                                        C.POINTER(C.c_uint64)]
+        lib.or_event_stream.restype = C.c_int
         lib.or_next_event_time.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_double]
         lib.or_next_event_time.restype = C.c_double
         lib.or_simulate_naive.argtypes = [C.c_void_p, C.c_uint64, u64p, C.c_uint64, u64p, f64p, u64p]
@@ -122,6 +128,9 @@ def alias_build(weights) -> tuple[np.ndarray, np.ndarray]:
     if rc != 0:
         raise ValueError(f"alias build failed ({rc})")
     return prob, alias
+
+
+EVENT_SPECIATION = 0xFFFFFFFF
 
 
 def richness(species) -> int:
@@ -255,6 +264,33 @@ class Scenario:
         if rc != 0:
             raise ValueError(f"simulate_culled failed ({rc})")
         return sp, int(ev.value), int(rounds.value)
+
+    def event_stream(self, seed: int, samples):
+        """The reduced event stream (sections on sorting events and reporting coalescence): every
+        event of the samples' lineages once, sorted by (t, origin), as arrays t, prior (the smallest
+        prior event time of its copies), origin and outcome (EVENT_SPECIATION for a speciation);
+        and the coalescences as arrays t, parent (the first lineage's arrival) and location, sorted
+        by (t, location, parent)."""
+        s = self._samples(samples)
+        n = len(s)
+        ne, nc = C.c_uint64(), C.c_uint64()
+        ev_cap, co_cap = 0, 0
+        while True:
+            et, ep = np.zeros(max(ev_cap, 1)), np.zeros(max(ev_cap, 1))
+            ef, eo = np.zeros(max(ev_cap, 1), np.uint32), np.zeros(max(ev_cap, 1), np.uint32)
+            ct, cp, cl = np.zeros(max(co_cap, 1)), np.zeros(max(co_cap, 1)), np.zeros(max(co_cap, 1), np.uint32)
+            rc = self._lib.or_event_stream(self._h, seed, _ptr(s, C.c_uint64), n, ev_cap, _ptr(et, C.c_double),
+                                           _ptr(ep, C.c_double), _ptr(ef, C.c_uint32), _ptr(eo, C.c_uint32), co_cap,
+                                           _ptr(ct, C.c_double), _ptr(cp, C.c_double), _ptr(cl, C.c_uint32),
+                                           C.byref(ne), C.byref(nc))
+            if rc != 0:
+                raise ValueError(f"event_stream failed ({rc})")
+            if ne.value <= ev_cap and nc.value <= co_cap:
+                break
+            ev_cap, co_cap = ne.value, nc.value
+        k, m = ne.value, nc.value
+        return (dict(t=et[:k], prior=ep[:k], origin=ef[:k], outcome=eo[:k]),
+                dict(t=ct[:m], parent=cp[:m], loc=cl[:m]))
 
     def trace(self, seed: int, sample: int, max_events: int = 1 << 16):
         """Event trace of one sample: (times, locations, dx, dy, speciated)."""

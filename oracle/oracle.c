@@ -38,7 +38,12 @@
  *           a linear search over the Poisson cdf, one uniform per count);
  *   [prot]  appendix "Protracted Speciation" (a speciation completes only
  *           after tau generations, so the draws at events younger than tau
- *           are ignored).
+ *           are ignored);
+ *   [evs]   sections "Sorting Events using the Water-Level Algorithm" and
+ *           "Reporting Coalescence Events Independently" (every lineage's
+ *           events in one stream sorted by event time, then prior event
+ *           time; copies of one event adjacent; the first copy is the
+ *           parent's, and a later distinct prior time marks a coalescence).
  */
 #include <math.h>
 #include <stdint.h>
@@ -712,3 +717,124 @@ OR_EXPORT uint64_t or_species_id(uint64_t seed, uint32_t loc, double t) {
 
 OR_EXPORT uint32_t or_sample_location(const or_scenario *s, uint64_t sample) { return sample_location(s, sample); }
 OR_EXPORT uint32_t or_scenario_cmax(const or_scenario *s) { return s->cmax; }
+
+/* ------------------------------------------------------------------------- */
+/* [evs] The event stream, from its definition: every sample's lineage is    */
+/* traced alone to its speciation and every event it goes through is listed  */
+/* as (event time t, prior event time, origin location, outcome: the new     */
+/* location or OR_EVENT_SPECIATION); the prior event time of a sample's      */
+/* first event is 0, the present.  Sorted by event time, then origin, then   */
+/* prior event time, the copies of one event made by lineages that share it  */
+/* are adjacent.  The reduced stream keeps each event once, with the         */
+/* smallest prior event time of its copies (the parent's); every further     */
+/* distinct prior event time among the copies is a coalescence: a lineage   */
+/* that arrived at the origin at that time found it occupied, by the lineage  */
+/* that arrived first.  Coalescences are listed as (time, parent's arrival,  */
+/* location) sorted by time, then location, then parent's arrival.           */
+/* Returns the counts; at most *_cap records are written to each output.     */
+/* -1 for an invalid sample id.                                               */
+/* ------------------------------------------------------------------------- */
+#define OR_EVENT_SPECIATION 0xFFFFFFFFu
+
+typedef struct {
+    double t, prior;
+    uint32_t from, to;
+} or_ev;
+
+typedef struct {
+    double t, parent;
+    uint32_t loc;
+} or_co;
+
+static int f64_cmp(double a, double b) { return a < b ? -1 : (a > b ? 1 : 0); }
+static int u32_cmp(uint32_t a, uint32_t b) { return a < b ? -1 : (a > b ? 1 : 0); }
+
+static int ev_cmp(const void *pa, const void *pb) {
+    const or_ev *a = (const or_ev *)pa, *b = (const or_ev *)pb;
+    int c = f64_cmp(a->t, b->t);
+    if (!c) c = u32_cmp(a->from, b->from);
+    if (!c) c = f64_cmp(a->prior, b->prior);
+    if (!c) c = u32_cmp(a->to, b->to);
+    return c;
+}
+
+static int co_cmp(const void *pa, const void *pb) {
+    const or_co *a = (const or_co *)pa, *b = (const or_co *)pb;
+    int c = f64_cmp(a->t, b->t);
+    if (!c) c = u32_cmp(a->loc, b->loc);
+    if (!c) c = f64_cmp(a->parent, b->parent);
+    return c;
+}
+
+OR_EXPORT int or_event_stream(or_scenario *s, uint64_t seed, const uint64_t *samples, uint64_t n, uint64_t ev_cap,
+                              double *ev_t, double *ev_prior, uint32_t *ev_from, uint32_t *ev_to, uint64_t co_cap,
+                              double *co_t, double *co_parent, uint32_t *co_loc, uint64_t *n_events,
+                              uint64_t *n_coalescences) {
+    uint64_t N = or_scenario_individuals(s);
+    for (uint64_t q = 0; q < n; ++q)
+        if (samples[q] >= N) return -1;
+    uint64_t len = 0, cap = 1024;
+    or_ev *all = (or_ev *)malloc(sizeof(or_ev) * cap);
+    if (!all) abort();
+    for (uint64_t q = 0; q < n; ++q) {
+        uint32_t loc = sample_location(s, samples[q]);
+        double prior = 0.0, t = or_next_event_time(s, seed, loc, 0.0);
+        for (;;) {
+            if (len == cap) {
+                cap *= 2;
+                all = (or_ev *)realloc(all, sizeof(or_ev) * cap);
+                if (!all) abort();
+            }
+            uint64_t sp = 0;
+            const uint32_t from = loc;
+            const int stop = commit_event(s, seed, &loc, t, &sp, NULL, NULL);
+            all[len].t = t;
+            all[len].prior = prior;
+            all[len].from = from;
+            all[len].to = stop ? OR_EVENT_SPECIATION : loc;
+            ++len;
+            if (stop) break;
+            prior = t;
+            t = or_next_event_time(s, seed, loc, t);
+        }
+    }
+    qsort(all, len, sizeof(or_ev), ev_cmp);
+    uint64_t co_len = n + 1;
+    or_co *co = (or_co *)malloc(sizeof(or_co) * co_len);
+    if (!co) abort();
+    uint64_t ne = 0, nc = 0, first = 0;
+    for (uint64_t i = 0; i < len; ++i) {
+        const int same_event = i > 0 && all[i].t == all[i - 1].t && all[i].from == all[i - 1].from;
+        if (!same_event) {
+            first = i;
+            if (ne < ev_cap) {
+                ev_t[ne] = all[i].t;
+                ev_prior[ne] = all[i].prior;
+                ev_from[ne] = all[i].from;
+                ev_to[ne] = all[i].to;
+            }
+            ++ne;
+        } else if (all[i].prior != all[i - 1].prior) {
+            if (nc == co_len) {
+                co_len *= 2;
+                co = (or_co *)realloc(co, sizeof(or_co) * co_len);
+                if (!co) abort();
+            }
+            co[nc].t = all[i].prior;
+            co[nc].parent = all[first].prior;
+            co[nc].loc = all[i].from;
+            ++nc;
+        }
+    }
+    qsort(co, nc, sizeof(or_co), co_cmp);
+    for (uint64_t k = 0; k < nc && k < co_cap; ++k) {
+        co_t[k] = co[k].t;
+        co_parent[k] = co[k].parent;
+        co_loc[k] = co[k].loc;
+    }
+    free(co);
+    free(all);
+    *n_events = ne;
+    *n_coalescences = nc;
+    return 0;
+}
