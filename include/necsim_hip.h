@@ -246,6 +246,61 @@ int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint64_
 int nh_batch_resume(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint64_t workspace_bytes,
                     const nh_config *cfg, nh_stats *stats, void *stream);
 
+/* Event stream (sections "Sorting Events using the Water-Level Algorithm" and
+ * "Reporting Coalescence Events Independently").  The stream of a simulation
+ * lists every event that the samples' lineages go through, each once, sorted
+ * by event time t and then origin: a dispersal from `origin` to `outcome`, or a
+ * speciation (outcome NH_EVENT_SPECIATION), with t_prior the time of the
+ * previous event of the first lineage to reach it (0 for a sample's first
+ * event).  Lineages that share an event have coalesced: a coalescence is the
+ * arrival of a lineage, at time t, at a location `loc` already holding another
+ * sampled lineage, which arrived there at t_parent (0: it was sampled there);
+ * they are listed sorted by t, loc, t_parent.  Every lineage ends in one
+ * speciation or one coalescence, so the distinct samples of a job number its
+ * speciation events plus its coalescences.  Locations are loc32 =
+ * (y*W + x)*C_max + i as for the speciation-event reporter. */
+#define NH_EVENT_SPECIATION 0xFFFFFFFFu
+typedef struct {
+    double t;
+    double t_prior;
+    uint32_t origin;
+    uint32_t outcome;
+} nh_event;
+
+typedef struct {
+    double t;
+    double t_parent;
+    uint32_t loc;
+    uint32_t reserved;
+} nh_coalescence;
+
+/* Per-job outputs: d_events (device, events_cap records; may be NULL with
+ * events_cap 0 to count only) and d_coalescences (device, room for the job's n
+ * records, never more are needed).  n_events and n_coalescences are set by the
+ * call; when n_events exceeds events_cap only the first events_cap events were
+ * written, and a second call with room for them all gives the whole stream. */
+typedef struct {
+    nh_event *d_events;
+    uint64_t events_cap;
+    nh_coalescence *d_coalescences;
+    uint64_t n_events;
+    uint64_t n_coalescences;
+} nh_stream_out;
+
+/* The event stream of every job of the batch run that just finished in
+ * d_workspace: jobs must be the run's own jobs (same scenarios, seeds and sample
+ * buffers, all still alive), the run complete (not suspended) and free of
+ * errors; the workspace is only read.  The library replays each lineage's
+ * committed events on the GPU, sorts the records with device radix sorts and
+ * reduces them to events and coalescences; it allocates its scratch
+ * stream-ordered (about 100 bytes per committed event, below 2^31 of them) and
+ * frees it before returning.  Synchronises `stream`.  Runs of the nh_server_*
+ * engine have no such workspace.  NH_EINVAL if the workspace holds no finished,
+ * error-free run of these jobs or the run committed 2^31 events or more;
+ * NH_EDEVICE on a HIP error (an allocation that fails included). */
+int nh_event_stream(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint64_t workspace_bytes,
+                    nh_stream_out *outs, void *stream);
+
 /* One job with device buffers; allocates its own workspace (hipMallocAsync on
  * the stream).  Same semantics as nh_batch_run with one job. */
 int nh_simulate_device(const nh_scenario *scenario, uint64_t seed, const uint64_t *d_sample_ids, uint64_t n,

@@ -67,6 +67,8 @@ def _load():
         lib.or_scenario_table.restype = C.c_uint32
         lib.or_sample_location.argtypes = [C.c_void_p, C.c_uint64]
         lib.or_sample_location.restype = C.c_uint32
+        lib.or_event_outcome.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_double]
+        lib.or_event_outcome.restype = C.c_uint32
         lib.or_scenario_create_implicit.argtypes = [C.c_uint32, C.c_uint32, C.c_double, C.c_double, C.c_double,
                                                     C.c_double, C.POINTER(C.c_void_p)]
         lib.or_scenario_create_implicit.restype = C.c_int
@@ -264,6 +266,10 @@ class Scenario:
         if rc != 0:
             raise ValueError(f"simulate_culled failed ({rc})")
         return sp, int(ev.value), int(rounds.value)
+
+    def event_outcome(self, seed: int, loc: int, t: float) -> int:
+        """Outcome of the event at (loc, t): the new location, or EVENT_SPECIATION."""
+        return int(self._lib.or_event_outcome(self._h, seed, loc, t))
 
     def event_stream(self, seed: int, samples):
         """The reduced event stream (sections on sorting events and reporting coalescence): every

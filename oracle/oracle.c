@@ -838,3 +838,10 @@ OR_EXPORT int or_event_stream(or_scenario *s, uint64_t seed, const uint64_t *sam
     *n_coalescences = nc;
     return 0;
 }
+
+/* Outcome of the event at (loc, t) ([ind] Summary): the new location, or      */
+/* OR_EVENT_SPECIATION.                                                       */
+OR_EXPORT uint32_t or_event_outcome(or_scenario *s, uint64_t seed, uint32_t loc, double t) {
+    uint64_t sp = 0;
+    return commit_event(s, seed, &loc, t, &sp, NULL, NULL) ? OR_EVENT_SPECIATION : loc;
+}

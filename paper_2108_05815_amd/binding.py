@@ -66,6 +66,17 @@ class nh_job(C.Structure):
                 ("d_abundance_counts_out", C.c_void_p)]
 
 
+class nh_stream_out(C.Structure):
+    _fields_ = [("d_events", C.c_void_p), ("events_cap", C.c_uint64), ("d_coalescences", C.c_void_p),
+                ("n_events", C.c_uint64), ("n_coalescences", C.c_uint64)]
+
+
+# nh_event and nh_coalescence records as numpy dtypes (24 bytes each)
+EVENT_DTYPE = np.dtype([("t", "<f8"), ("t_prior", "<f8"), ("origin", "<u4"), ("outcome", "<u4")])
+COALESCENCE_DTYPE = np.dtype([("t", "<f8"), ("t_parent", "<f8"), ("loc", "<u4"), ("reserved", "<u4")])
+NH_EVENT_SPECIATION = 0xFFFFFFFF
+
+
 class nh_server_config(C.Structure):
     _fields_ = [("lineage_capacity", C.c_uint64), ("max_jobs", C.c_uint32), ("lookahead", C.c_uint32),
                 ("cfg", nh_config)]
@@ -100,6 +111,9 @@ _lib.nh_batch_run.argtypes = [C.POINTER(nh_job), C.c_uint32, C.c_void_p, C.c_uin
 _lib.nh_batch_run.restype = C.c_int
 _lib.nh_batch_resume.argtypes = _lib.nh_batch_run.argtypes
 _lib.nh_batch_resume.restype = C.c_int
+_lib.nh_event_stream.argtypes = [C.POINTER(nh_job), C.c_uint32, C.c_void_p, C.c_uint64, C.POINTER(nh_stream_out),
+                                 C.c_void_p]
+_lib.nh_event_stream.restype = C.c_int
 _lib.nh_simulate_device.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
                                     C.POINTER(nh_config), C.POINTER(nh_stats), C.c_void_p]
 _lib.nh_simulate_device.restype = C.c_int
@@ -139,6 +153,7 @@ nh_workspace_bytes = _lib.nh_workspace_bytes
 nh_scenario_footprint_bytes = _lib.nh_scenario_footprint_bytes
 nh_batch_run = _lib.nh_batch_run
 nh_batch_resume = _lib.nh_batch_resume
+nh_event_stream = _lib.nh_event_stream
 nh_simulate_device = _lib.nh_simulate_device
 nh_simulate = _lib.nh_simulate
 nh_last_error = _lib.nh_last_error
@@ -154,7 +169,7 @@ nh_server_drain = _lib.nh_server_drain
 nh_server_destroy = _lib.nh_server_destroy
 
 EXPORTED = ["nh_scenario_create", "nh_scenario_create_implicit", "nh_scenario_destroy", "nh_scenario_individuals", "nh_scenario_table_bytes",
-            "nh_workspace_bytes", "nh_scenario_footprint_bytes", "nh_batch_run", "nh_batch_resume",
+            "nh_workspace_bytes", "nh_scenario_footprint_bytes", "nh_batch_run", "nh_batch_resume", "nh_event_stream",
             "nh_simulate_device",
             "nh_simulate", "nh_last_error", "nh_version", "nh_server_bytes", "nh_server_create",
             "nh_server_submit", "nh_server_progress", "nh_server_poll", "nh_server_drain", "nh_server_destroy",
@@ -376,6 +391,47 @@ def batch_run(jobs, workspace, config: nh_config | None = None, stream=None):
 def batch_resume(jobs, workspace, config: nh_config | None = None, stream=None):
     """nh_batch_resume: continue a suspended run from the state in `workspace` (the same jobs)."""
     return _batch(_lib.nh_batch_resume, "nh_batch_resume", jobs, workspace, config, stream)
+
+
+def event_stream(jobs, workspace, events_cap=None, stream=None):
+    """nh_event_stream for the jobs of the batch run that just finished in `workspace` (the same job
+    tuples as given to batch_run).  events_cap: records of room per job (a list, or one int for all);
+    None counts first and then makes room for every event.  Returns per job (events, coalescences) as
+    numpy arrays of EVENT_DTYPE and COALESCENCE_DTYPE, plus the total counts (n_events may exceed
+    the room given)."""
+    import torch
+
+    arr = (nh_job * len(jobs))()
+    for k, job in enumerate(jobs):
+        arr[k] = _job(*job)
+    dev = workspace.device
+    s = stream if stream is not None else torch.cuda.current_stream()
+    if events_cap is None:
+        outs = (nh_stream_out * len(jobs))()
+        co = [torch.empty(max(int(job[2].numel()), 1) * COALESCENCE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+              for job in jobs]
+        for k in range(len(jobs)):
+            outs[k] = nh_stream_out(None, 0, co[k].data_ptr(), 0, 0)
+        _check(_lib.nh_event_stream(arr, len(jobs), workspace.data_ptr(), workspace.numel(), outs,
+                                    C.c_void_p(s.cuda_stream)), "nh_event_stream")
+        events_cap = [int(o.n_events) for o in outs]
+    if isinstance(events_cap, int):
+        events_cap = [events_cap] * len(jobs)
+    ev = [torch.empty(max(cap, 1) * EVENT_DTYPE.itemsize, dtype=torch.uint8, device=dev) for cap in events_cap]
+    co = [torch.empty(max(int(job[2].numel()), 1) * COALESCENCE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+          for job in jobs]
+    outs = (nh_stream_out * len(jobs))()
+    for k in range(len(jobs)):
+        outs[k] = nh_stream_out(ev[k].data_ptr(), events_cap[k], co[k].data_ptr(), 0, 0)
+    _check(_lib.nh_event_stream(arr, len(jobs), workspace.data_ptr(), workspace.numel(), outs,
+                                C.c_void_p(s.cuda_stream)), "nh_event_stream")
+    res = []
+    for k in range(len(jobs)):
+        ne, nc = int(outs[k].n_events), int(outs[k].n_coalescences)
+        e = ev[k].cpu().numpy().view(EVENT_DTYPE)[:min(ne, events_cap[k])]
+        c = co[k].cpu().numpy().view(COALESCENCE_DTYPE)[:nc]
+        res.append(dict(events=e, coalescences=c, n_events=ne, n_coalescences=nc))
+    return res
 
 
 def measure_mix_peak(stream=None) -> float:

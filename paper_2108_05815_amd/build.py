@@ -13,6 +13,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "necsim_hip.hip")
+# hipCUB sort and scan instantiations for the event stream (own translation unit)
+SORT_SRC = os.path.join(HERE, "csrc", "stream_sort.hip")
 HEADER = os.path.join(ROOT, "include", "necsim_hip.h")
 LIB = os.path.join(HERE, "libnecsim_hip.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -29,7 +31,7 @@ FLAGS = [
 def build(verbose: bool = False, extra=None) -> str:
     """Compile the HIP library every time it is called; returns the .so path."""
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [HIPCC, *FLAGS, *(extra or []), SRC, "-o", tmp]
+    cmd = [HIPCC, *FLAGS, *(extra or []), SRC, SORT_SRC, "-o", tmp]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.run(cmd, check=True)

@@ -44,6 +44,7 @@
 #include <vector>
 
 #include "necsim_hip.h"
+#include "stream_sort.h"
 
 #define NH_API extern "C" __attribute__((visibility("default")))
 
@@ -1015,6 +1016,19 @@ __device__ __forceinline__ void wave_retire(Ctl *ctl, JobState *js, uint32_t *ri
     }
 }
 
+// Location of dense individual id (< N): the cell whose capacity prefix holds
+// it, and the id's offset in that cell as the deme index.
+__device__ __forceinline__ uint32_t sample_loc(const JobDev *__restrict__ J, const JobView &v, uint64_t id) {
+    const uint32_t cells = v.W * v.H;
+    uint32_t lo = 0, hi = cells; // last cell with prefix <= id
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (J->prefix[mid] <= id) lo = mid;
+        else hi = mid;
+    }
+    return lo * v.cmax + (uint32_t)(id - J->prefix[lo]);
+}
+
 // Lineage init: dense sample id -> (cell, deme index) -> loc; first event time
 // from t = 0; append to the current round's queue.  Lineages [g_begin, g_end)
 // belong to job `fixed_job`, or (fixed_job < 0) to the job found by binary
@@ -1039,14 +1053,7 @@ __global__ void k_init(Ctl *ctl, const JobDev *__restrict__ jobs, uint32_t n_job
             atomicOr(&js[jb].flags, kJobBadSample);
             bad = true;
         } else {
-            const uint32_t cells = v.W * v.H;
-            uint32_t lo = 0, hi = cells; // last cell with prefix <= id
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (J->prefix[mid] <= id) lo = mid;
-                else hi = mid;
-            }
-            loc = lo * v.cmax + (uint32_t)(id - J->prefix[lo]);
+            loc = sample_loc(J, v, id);
             t = next_event_time(v, loc, 0.0, &ctl->error, cnt);
             push = t >= 0.0;
             bad = !push;
@@ -1539,6 +1546,183 @@ __global__ void k_resolve(const JobDev *__restrict__ jobs, JobState *js, Lin lin
     }
 }
 
+// ---------------------------------------------------------------------------
+// Event stream (sections "Sorting Events using the Water-Level Algorithm" and
+// "Reporting Coalescence Events Independently").  After a completed run each
+// lineage knows how many events it committed (redundant copies of an event it
+// shared with another lineage included) and whether it stopped by merging.
+// Replaying those events from the sample's start gives one record (t, prior
+// event time, origin, outcome) per committed event; a merged lineage adds one
+// record for the state it was merged at (its next event, committed by the
+// lineage it merged into).  Every lineage that reaches an event leaves a copy
+// of it with its own prior event time, so after a stable sort by (job, t,
+// origin, prior) the first copy of each event carries the parent's prior time
+// and every further distinct prior time is the arrival of a lineage that found
+// the origin occupied: a coalescence.  That is the same reduced stream as
+// tracing every sample alone to its speciation, without the redundant work.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kRecMerged = 0xFFFFFFFEu; // outcome of a merge-state record
+constexpr uint32_t kErrStream = 8u;          // a replay did not retrace its lineage
+
+struct StreamRecs {   // one entry per record (structure of arrays)
+    uint64_t *t;      // bits of the event time (non-negative doubles order as their bits)
+    uint64_t *prior;  // bits of the prior event time
+    uint32_t *from;   // origin location
+    uint32_t *to;     // new location, NH_EVENT_SPECIATION or kRecMerged
+    uint32_t *job;
+};
+
+struct StreamDev {    // per-job outputs
+    nh_event *ev;
+    uint64_t ev_cap;
+    nh_coalescence *co;
+    uint64_t co_cap;
+};
+
+__device__ __forceinline__ bool stream_bad(const JobDev *__restrict__ J, uint32_t g) {
+    return J->samples[g - J->lin_base] >= J->n_individuals;
+}
+
+// Records per lineage: its committed events, plus one if it was merged.
+__global__ void k_stream_count(const JobDev *__restrict__ jobs, Lin lin, uint32_t n_total, uint64_t *n_rec) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_total) return;
+    const JobDev *J = &jobs[lin.job[g]];
+    n_rec[g] = stream_bad(J, g) ? 0ull : (uint64_t)lin.events[g] + (lin.parent[g] != g ? 1ull : 0ull);
+}
+
+// Replays lineage g's committed events into records off[g] ..; one lane per lineage.
+__global__ void k_stream_replay(const JobDev *__restrict__ jobs, Lin lin, uint32_t n_total,
+                                const uint64_t *__restrict__ off, StreamRecs R, uint32_t *err) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_total) return;
+    const uint32_t jb = lin.job[g];
+    const JobDev *J = &jobs[jb];
+    if (stream_bad(J, g)) return;
+    const JobView v = load_view(J);
+    Counters cnt;
+    Pos p = pos_from_loc(v, sample_loc(J, v, J->samples[g - J->lin_base]));
+    double t = next_event_time(v, p.loc, 0.0, err, cnt), prior = 0.0;
+    uint64_t o = off[g];
+    const uint32_t n_ev = lin.events[g];
+    const bool merged = lin.parent[g] != g;
+    for (uint32_t k = 0; k < n_ev; ++k) {
+        if (t < 0.0) { // runaway search (flagged by next_event_time)
+            atomicOr(err, kErrStream);
+            return;
+        }
+        const uint32_t from = p.loc;
+        const bool spec = commit_event<false>(v, p, t, cnt);
+        R.t[o] = (uint64_t)__double_as_longlong(t);
+        R.prior[o] = (uint64_t)__double_as_longlong(prior);
+        R.from[o] = from;
+        R.to[o] = spec ? NH_EVENT_SPECIATION : p.loc;
+        R.job[o] = jb;
+        ++o;
+        if (spec) {
+            // only a representative's last event speciates
+            if (k + 1 != n_ev || merged) atomicOr(err, kErrStream);
+            return;
+        }
+        prior = t;
+        t = next_event_time(v, p.loc, t, err, cnt);
+    }
+    if (!merged || t < 0.0) {
+        atomicOr(err, kErrStream); // a representative must have ended by speciating
+        return;
+    }
+    R.t[o] = (uint64_t)__double_as_longlong(t);
+    R.prior[o] = (uint64_t)__double_as_longlong(prior);
+    R.from[o] = p.loc;
+    R.to[o] = kRecMerged;
+    R.job[o] = jb;
+}
+
+__global__ void k_iota(uint32_t *v, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) v[i] = i;
+}
+
+template <typename T>
+__global__ void k_gather(const T *__restrict__ src, const uint32_t *__restrict__ perm, T *__restrict__ dst,
+                         uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[perm[i]];
+}
+
+__device__ __forceinline__ bool same_event(const StreamRecs &R, uint32_t a, uint32_t b) {
+    return R.job[a] == R.job[b] && R.t[a] == R.t[b] && R.from[a] == R.from[b];
+}
+
+// Over the sorted records: the first copy of an event, and the copies whose prior
+// time differs from the previous copy's (coalescences); counts per job.
+__global__ void k_stream_flags(StreamRecs R, const uint32_t *__restrict__ perm, uint32_t n, uint32_t *flag_ev,
+                               uint32_t *flag_co, unsigned long long *ev_count, unsigned long long *co_count) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t e = perm[i];
+        const bool first = i == 0 || !same_event(R, perm[i - 1], e);
+        const bool coal = !first && R.prior[perm[i - 1]] != R.prior[e];
+        flag_ev[i] = first;
+        flag_co[i] = coal;
+        if (first) atomicAdd(&ev_count[R.job[e]], 1ull);
+        if (coal) atomicAdd(&co_count[R.job[e]], 1ull);
+    }
+}
+
+// Writes each event (its first copy, the outcome of a copy that committed it)
+// at its rank within the job, and gathers the coalescences, each with the
+// prior time of its event's first copy (the parent's arrival).
+__global__ void k_stream_emit(StreamRecs R, const uint32_t *__restrict__ perm, uint32_t n,
+                              const uint32_t *__restrict__ flag_ev, const uint32_t *__restrict__ rank_ev,
+                              const uint32_t *__restrict__ flag_co, const uint32_t *__restrict__ rank_co,
+                              const uint64_t *__restrict__ ev_base, const StreamDev *__restrict__ outs,
+                              StreamRecs C, uint32_t *err) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t e = perm[i];
+        if (flag_ev[i]) {
+            const uint32_t jb = R.job[e];
+            const uint64_t local = rank_ev[i] - ev_base[jb];
+            if (local < outs[jb].ev_cap) {
+                uint32_t k = i;
+                while (k < n && same_event(R, perm[k], e) && R.to[perm[k]] == kRecMerged) ++k;
+                const bool found = k < n && same_event(R, perm[k], e);
+                if (!found) atomicOr(err, kErrStream);
+                nh_event out;
+                out.t = __longlong_as_double((long long)R.t[e]);
+                out.t_prior = __longlong_as_double((long long)R.prior[e]);
+                out.origin = R.from[e];
+                out.outcome = found ? R.to[perm[k]] : NH_EVENT_SPECIATION;
+                outs[jb].ev[local] = out;
+            }
+        }
+        if (flag_co[i]) {
+            uint32_t k = i;
+            while (k > 0 && same_event(R, perm[k - 1], e)) --k;
+            const uint32_t c = rank_co[i];
+            C.t[c] = R.prior[e];
+            C.prior[c] = R.prior[perm[k]];
+            C.from[c] = R.from[e];
+            C.job[c] = R.job[e];
+        }
+    }
+}
+
+// Writes the sorted coalescences at their rank within the job.
+__global__ void k_stream_coal_write(StreamRecs C, const uint32_t *__restrict__ perm, uint32_t n,
+                                    const uint64_t *__restrict__ co_base, const StreamDev *__restrict__ outs) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t e = perm[i];
+        const uint32_t jb = C.job[e];
+        const uint64_t local = i - co_base[jb];
+        if (local < outs[jb].co_cap) {
+            nh_coalescence out;
+            out.t = __longlong_as_double((long long)C.t[e]);
+            out.t_parent = __longlong_as_double((long long)C.prior[e]);
+            out.loc = C.from[e];
+            out.reserved = 0;
+            outs[jb].co[local] = out;
+        }
+    }
+}
+
 // Abundance reporter: every occupied slot of the species sets of jobs
 // [j_lo, j_hi) (contiguous in the species-set area, n_slots in all) appends its
 // (species, samples) pair to its job's output.
@@ -1853,6 +2037,26 @@ Workspace layout(uint64_t n_total, uint32_t n_jobs) {
     w.off_rcount = take(4 * (4 * N + 64ull * std::max<uint32_t>(n_jobs, 1)));
     w.total = o;
     return w;
+}
+
+// The lineage arrays of a batch workspace.
+Lin lin_view(char *ws, const Workspace &L) {
+    Lin lin;
+    lin.loc[0] = (uint32_t *)(ws + L.off_loc0);
+    lin.loc[1] = (uint32_t *)(ws + L.off_loc1);
+    lin.t[0] = (double *)(ws + L.off_t0);
+    lin.t[1] = (double *)(ws + L.off_t1);
+    lin.parent = (uint32_t *)(ws + L.off_parent);
+    lin.species = (unsigned long long *)(ws + L.off_species);
+    lin.job = (uint32_t *)(ws + L.off_job);
+    lin.events = (uint32_t *)(ws + L.off_events);
+    lin.spec_loc = (uint32_t *)(ws + L.off_sloc);
+    lin.spec_t = (double *)(ws + L.off_st);
+    lin.act[0] = (uint32_t *)(ws + L.off_act0);
+    lin.act[1] = (uint32_t *)(ws + L.off_act1);
+    lin.hash = (unsigned long long *)(ws + L.off_hash);
+    lin.hmask = (uint32_t)(L.hcap - 1);
+    return lin;
 }
 
 struct PinnedStatus {
@@ -2203,21 +2407,7 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
     double *d_htab = (double *)(ws + L.off_htab);
     uint32_t *d_ring = (uint32_t *)(ws + L.off_ring);
     const uint32_t ring_cap = std::max<uint32_t>(n_jobs, 1);
-    Lin lin;
-    lin.loc[0] = (uint32_t *)(ws + L.off_loc0);
-    lin.loc[1] = (uint32_t *)(ws + L.off_loc1);
-    lin.t[0] = (double *)(ws + L.off_t0);
-    lin.t[1] = (double *)(ws + L.off_t1);
-    lin.parent = (uint32_t *)(ws + L.off_parent);
-    lin.species = (unsigned long long *)(ws + L.off_species);
-    lin.job = (uint32_t *)(ws + L.off_job);
-    lin.events = (uint32_t *)(ws + L.off_events);
-    lin.spec_loc = (uint32_t *)(ws + L.off_sloc);
-    lin.spec_t = (double *)(ws + L.off_st);
-    lin.act[0] = (uint32_t *)(ws + L.off_act0);
-    lin.act[1] = (uint32_t *)(ws + L.off_act1);
-    lin.hash = (unsigned long long *)(ws + L.off_hash);
-    lin.hmask = (uint32_t)(L.hcap - 1);
+    const Lin lin = lin_view(ws, L);
     unsigned long long *rich = (unsigned long long *)(ws + L.off_rich);
     uint32_t *rich_counts = (uint32_t *)(ws + L.off_rcount);
 
@@ -2512,6 +2702,226 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
     return suspended ? NH_SUSPENDED : NH_OK;
 }
 
+// Stream-ordered scratch allocations of one call, released (stream-ordered)
+// when the call returns.
+struct AsyncScratch {
+    hipStream_t stream;
+    std::vector<void *> held;
+    ~AsyncScratch() {
+        for (void *q : held) (void)hipFreeAsync(q, stream);
+    }
+    template <typename T>
+    int take(T *&out, uint64_t count) {
+        void *q = nullptr;
+        HIP_TRY(hipMallocAsync(&q, std::max<uint64_t>(count, 1) * sizeof(T), stream));
+        held.push_back(q);
+        out = (T *)q;
+        return 0;
+    }
+};
+
+// Scratch bytes the sorts and scans over n items need.
+int sort_scratch_bytes(uint32_t n, size_t &bytes) {
+    size_t a = 0, b = 0, c = 0;
+    HIP_TRY(nh_sort::sort_pairs_u64(nullptr, a, nullptr, nullptr, nullptr, nullptr, n, 64, nullptr));
+    HIP_TRY(nh_sort::sort_pairs_u32(nullptr, b, nullptr, nullptr, nullptr, nullptr, n, 32, nullptr));
+    HIP_TRY(nh_sort::exclusive_sum_u32(nullptr, c, nullptr, nullptr, n, nullptr));
+    bytes = std::max(a, std::max(b, c));
+    return 0;
+}
+
+// Stable LSD passes: perm (initially the identity) ends sorted by (job, key2,
+// key1, key0) over the records' fields; returns the array holding the result.
+int stream_sort(const StreamRecs &R, uint32_t n, uint32_t n_jobs, const uint64_t *key0_64, const uint32_t *key1_32,
+                const uint64_t *key2_64, uint32_t *perm_a, uint32_t *perm_b, uint64_t *k64_a, uint64_t *k64_b,
+                uint32_t *k32_a, uint32_t *k32_b, void *tmp, size_t tmp_bytes, hipStream_t stream,
+                uint32_t *&sorted) {
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((n + 255) / 256, 65535);
+    size_t b = tmp_bytes;
+    k_iota<<<blocks, 256, 0, stream>>>(perm_a, n);
+    HIP_TRY(nh_sort::sort_pairs_u64(tmp, b, key0_64, k64_b, perm_a, perm_b, n, 64, stream));
+    k_gather<uint32_t><<<blocks, 256, 0, stream>>>(key1_32, perm_b, k32_a, n);
+    b = tmp_bytes;
+    HIP_TRY(nh_sort::sort_pairs_u32(tmp, b, k32_a, k32_b, perm_b, perm_a, n, 32, stream));
+    k_gather<uint64_t><<<blocks, 256, 0, stream>>>(key2_64, perm_a, k64_a, n);
+    b = tmp_bytes;
+    HIP_TRY(nh_sort::sort_pairs_u64(tmp, b, k64_a, k64_b, perm_a, perm_b, n, 64, stream));
+    sorted = perm_b;
+    if (n_jobs > 1) {
+        int bits = 0;
+        while (bits < 32 && ((n_jobs - 1) >> bits) != 0) ++bits;
+        k_gather<uint32_t><<<blocks, 256, 0, stream>>>(R.job, perm_b, k32_a, n);
+        b = tmp_bytes;
+        HIP_TRY(nh_sort::sort_pairs_u32(tmp, b, k32_a, k32_b, perm_b, perm_a, n, bits, stream));
+        sorted = perm_a;
+    }
+    HIP_TRY(hipGetLastError());
+    return 0;
+}
+
+int event_stream_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint64_t workspace_bytes,
+                      nh_stream_out *outs, void *stream_ptr) {
+    hipStream_t stream = (hipStream_t)stream_ptr;
+    if (n_jobs == 0 || !jobs || !outs) return fail(NH_EINVAL, "no jobs or no outputs");
+    uint64_t n_total = 0;
+    for (uint32_t j = 0; j < n_jobs; ++j) {
+        if (!jobs[j].scenario) return fail(NH_EINVAL, "job %u has no scenario", j);
+        if (outs[j].events_cap && !outs[j].d_events) return fail(NH_EINVAL, "job %u: events_cap > 0 with NULL d_events", j);
+        if (jobs[j].n && !outs[j].d_coalescences) return fail(NH_EINVAL, "job %u has NULL d_coalescences", j);
+        n_total += jobs[j].n;
+    }
+    if (n_total >= (1ull << 31)) return fail(NH_EINVAL, "more than 2^31 - 1 samples in one batch");
+    const Workspace L = layout(n_total, n_jobs);
+    if (!d_workspace || workspace_bytes < L.total)
+        return fail(NH_ENOMEM, "workspace of %llu bytes is smaller than the %llu of this batch",
+                    (unsigned long long)workspace_bytes, (unsigned long long)L.total);
+    if (((uintptr_t)d_workspace & 255) != 0) return fail(NH_EINVAL, "workspace must be 256-byte aligned");
+    char *ws = (char *)d_workspace;
+    const Ctl *ctl = (const Ctl *)(ws + L.off_ctl);
+    const JobDev *d_jobs = (const JobDev *)(ws + L.off_jobs);
+    const JobState *d_js = (const JobState *)(ws + L.off_js);
+
+    // The workspace must hold a finished, error-free run of exactly these jobs.
+    Ctl hc;
+    std::vector<JobDev> hd(n_jobs);
+    std::vector<JobState> hs(n_jobs);
+    HIP_TRY(hipMemcpyAsync(&hc, ctl, sizeof hc, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(hd.data(), d_jobs, sizeof(JobDev) * n_jobs, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(hs.data(), d_js, sizeof(JobState) * n_jobs, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (hc.n_jobs != n_jobs) return fail(NH_EINVAL, "the workspace does not hold a run of these %u jobs", n_jobs);
+    if (hc.error) return fail(NH_EINVAL, "the run in the workspace failed (error flags %#x)", hc.error);
+    for (uint32_t j = 0; j < n_jobs; ++j) {
+        if (hd[j].seed != jobs[j].seed || hd[j].samples != jobs[j].d_sample_ids || hd[j].n != jobs[j].n ||
+            hd[j].table != jobs[j].scenario->d_table || hd[j].tau_t != jobs[j].scenario->tau_t)
+            return fail(NH_EINVAL, "job %u differs from the run in the workspace", j);
+        if (hs[j].remaining != 0)
+            return fail(NH_EINVAL, "the run in the workspace has not finished (job %u; suspended?)", j);
+        outs[j].n_events = 0;
+        outs[j].n_coalescences = 0;
+    }
+    if (n_total == 0) return NH_OK;
+    const Lin lin = lin_view(ws, L);
+    const uint32_t nt = (uint32_t)n_total;
+    const uint32_t lin_blocks = (nt + 255) / 256;
+    AsyncScratch S{stream, {}};
+
+    // Records per lineage and their offsets.
+    uint64_t *n_rec = nullptr, *off = nullptr;
+    uint32_t *err = nullptr;
+    if (int rc = S.take(n_rec, nt)) return rc;
+    if (int rc = S.take(off, nt)) return rc;
+    if (int rc = S.take(err, 1)) return rc;
+    HIP_TRY(hipMemsetAsync(err, 0, sizeof(uint32_t), stream));
+    k_stream_count<<<lin_blocks, 256, 0, stream>>>(d_jobs, lin, nt, n_rec);
+    size_t scan_bytes = 0;
+    HIP_TRY(nh_sort::exclusive_sum_u64(nullptr, scan_bytes, n_rec, off, nt, stream));
+    char *scan_tmp = nullptr;
+    if (int rc = S.take(scan_tmp, scan_bytes)) return rc;
+    HIP_TRY(nh_sort::exclusive_sum_u64(scan_tmp, scan_bytes, n_rec, off, nt, stream));
+    uint64_t last[2];
+    HIP_TRY(hipMemcpyAsync(&last[0], off + (nt - 1), sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(&last[1], n_rec + (nt - 1), sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    const uint64_t n_records = last[0] + last[1];
+    if (n_records >= (1ull << 31)) return fail(NH_EINVAL, "%llu event records exceed 2^31 - 1",
+                                              (unsigned long long)n_records);
+    if (n_records == 0) return NH_OK;
+    const uint32_t nr = (uint32_t)n_records;
+    const uint32_t rec_blocks = (uint32_t)std::min<uint64_t>((nr + 255) / 256, 65535);
+
+    // Replay, then sort by (job, t, origin, prior).
+    StreamRecs R;
+    if (int rc = S.take(R.t, nr)) return rc;
+    if (int rc = S.take(R.prior, nr)) return rc;
+    if (int rc = S.take(R.from, nr)) return rc;
+    if (int rc = S.take(R.to, nr)) return rc;
+    if (int rc = S.take(R.job, nr)) return rc;
+    // a replay that fails leaves records unwritten: their job index must still be valid
+    HIP_TRY(hipMemsetAsync(R.job, 0, sizeof(uint32_t) * nr, stream));
+    k_stream_replay<<<lin_blocks, 256, 0, stream>>>(d_jobs, lin, nt, off, R, err);
+    uint32_t *perm_a, *perm_b, *k32_a, *k32_b, *flag_ev, *flag_co, *rank_ev, *rank_co;
+    uint64_t *k64_a, *k64_b;
+    for (uint32_t **q : {&perm_a, &perm_b, &k32_a, &k32_b, &flag_ev, &flag_co, &rank_ev, &rank_co})
+        if (int rc = S.take(*q, nr)) return rc;
+    if (int rc = S.take(k64_a, nr)) return rc;
+    if (int rc = S.take(k64_b, nr)) return rc;
+    size_t tmp_bytes = 0;
+    if (int rc = sort_scratch_bytes(nr, tmp_bytes)) return rc;
+    char *tmp = nullptr;
+    if (int rc = S.take(tmp, tmp_bytes)) return rc;
+    uint32_t *sorted = nullptr;
+    if (int rc = stream_sort(R, nr, n_jobs, R.prior, R.from, R.t, perm_a, perm_b, k64_a, k64_b, k32_a, k32_b, tmp,
+                             tmp_bytes, stream, sorted))
+        return rc;
+
+    // Reduce: events and coalescences per job.
+    unsigned long long *counts = nullptr; // [0, n_jobs) events, [n_jobs, 2 n_jobs) coalescences
+    if (int rc = S.take(counts, 2ull * n_jobs)) return rc;
+    k_fill_u64<<<std::max<uint32_t>(1, (2 * n_jobs + 255) / 256), 256, 0, stream>>>(counts, 2ull * n_jobs, 0ull);
+    k_stream_flags<<<rec_blocks, 256, 0, stream>>>(R, sorted, nr, flag_ev, flag_co, counts, counts + n_jobs);
+    size_t b = tmp_bytes;
+    HIP_TRY(nh_sort::exclusive_sum_u32(tmp, b, flag_ev, rank_ev, nr, stream));
+    b = tmp_bytes;
+    HIP_TRY(nh_sort::exclusive_sum_u32(tmp, b, flag_co, rank_co, nr, stream));
+    std::vector<unsigned long long> hcnt(2ull * n_jobs);
+    HIP_TRY(hipMemcpyAsync(hcnt.data(), counts, sizeof(unsigned long long) * 2 * n_jobs, hipMemcpyDeviceToHost,
+                           stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    std::vector<uint64_t> base(2ull * n_jobs);
+    uint64_t n_coal = 0, ev_acc = 0;
+    for (uint32_t j = 0; j < n_jobs; ++j) {
+        base[j] = ev_acc;
+        base[n_jobs + j] = n_coal;
+        ev_acc += hcnt[j];
+        n_coal += hcnt[n_jobs + j];
+        if (hcnt[n_jobs + j] > jobs[j].n) return fail(NH_EDEVICE, "job %u: more coalescences than samples", j);
+    }
+    std::vector<StreamDev> hout(n_jobs);
+    for (uint32_t j = 0; j < n_jobs; ++j)
+        hout[j] = StreamDev{outs[j].d_events, outs[j].d_events ? outs[j].events_cap : 0, outs[j].d_coalescences,
+                            jobs[j].n};
+    uint64_t *d_base = nullptr;
+    StreamDev *d_out = nullptr;
+    if (int rc = S.take(d_base, 2ull * n_jobs)) return rc;
+    if (int rc = S.take(d_out, n_jobs)) return rc;
+    HIP_TRY(hipMemcpyAsync(d_base, base.data(), sizeof(uint64_t) * 2 * n_jobs, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(d_out, hout.data(), sizeof(StreamDev) * n_jobs, hipMemcpyHostToDevice, stream));
+    StreamRecs C{};
+    const uint32_t nc = (uint32_t)n_coal;
+    if (int rc = S.take(C.t, nc)) return rc;
+    if (int rc = S.take(C.prior, nc)) return rc;
+    if (int rc = S.take(C.from, nc)) return rc;
+    if (int rc = S.take(C.job, nc)) return rc;
+    k_stream_emit<<<rec_blocks, 256, 0, stream>>>(R, sorted, nr, flag_ev, rank_ev, flag_co, rank_co, d_base, d_out,
+                                                  C, err);
+    if (nc) {
+        // coalescences by (job, t, loc, parent's arrival)
+        size_t need = 0;
+        if (int rc = sort_scratch_bytes(nc, need)) return rc;
+        if (need > tmp_bytes) {
+            if (int rc = S.take(tmp, need)) return rc;
+            tmp_bytes = need;
+        }
+        uint32_t *csorted = nullptr;
+        if (int rc = stream_sort(C, nc, n_jobs, C.prior, C.from, C.t, perm_a, perm_b, k64_a, k64_b, k32_a, k32_b,
+                                 tmp, tmp_bytes, stream, csorted))
+            return rc;
+        k_stream_coal_write<<<(uint32_t)std::min<uint64_t>((nc + 255) / 256, 65535), 256, 0, stream>>>(
+            C, csorted, nc, d_base + n_jobs, d_out);
+    }
+    HIP_TRY(hipGetLastError());
+    uint32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, err, sizeof herr, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (herr) return fail(NH_EDEVICE, "event stream: a replay did not retrace its lineage (flags %#x)", herr);
+    for (uint32_t j = 0; j < n_jobs; ++j) {
+        outs[j].n_events = hcnt[j];
+        outs[j].n_coalescences = hcnt[n_jobs + j];
+    }
+    return NH_OK;
+}
+
 } // namespace
 
 NH_API int nh_batch_run(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint64_t workspace_bytes,
@@ -2523,6 +2933,11 @@ NH_API int nh_batch_resume(const nh_job *jobs, uint32_t n_jobs, void *d_workspac
                            const nh_config *cfg, nh_stats *stats, void *stream) {
     if (n_jobs == 0) return fail(NH_EINVAL, "no jobs to resume");
     return batch_run_impl(jobs, n_jobs, d_workspace, workspace_bytes, cfg, stats, stream, true);
+}
+
+NH_API int nh_event_stream(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint64_t workspace_bytes,
+                           nh_stream_out *outs, void *stream) {
+    return event_stream_impl(jobs, n_jobs, d_workspace, workspace_bytes, outs, stream);
 }
 
 NH_API int nh_simulate_device(const nh_scenario *scenario, uint64_t seed, const uint64_t *d_sample_ids, uint64_t n,

@@ -104,6 +104,25 @@ def test_resume_rejects_bad_calls_before_touching_the_gpu(B):
     assert B.nh_batch_resume(None, 1, None, 0, None, None, None) == B.NH_EINVAL
 
 
+def test_event_stream_rejects_bad_calls_before_touching_the_gpu(B):
+    from paper_2108_05815_amd import binding as bd
+    assert B.nh_event_stream(None, 0, None, 0, None, None) == B.NH_EINVAL
+    stand_in = C.create_string_buffer(64)  # a non-NULL scenario handle these checks never read
+    jobs = (bd.nh_job * 1)()
+    jobs[0].scenario = C.addressof(stand_in)
+    jobs[0].seed, jobs[0].n, jobs[0].d_sample_ids, jobs[0].d_species_out = 1, 4, 256, 256
+    outs = (bd.nh_stream_out * 1)()
+    assert B.nh_event_stream(jobs, 1, None, 0, None, None) == B.NH_EINVAL           # no outputs
+    outs[0].events_cap = 8                                                        # room but no buffer
+    outs[0].d_coalescences = 256
+    assert B.nh_event_stream(jobs, 1, None, 0, outs, None) == B.NH_EINVAL
+    outs[0].events_cap, outs[0].d_coalescences = 0, None                          # no coalescence buffer
+    assert B.nh_event_stream(jobs, 1, None, 0, outs, None) == B.NH_EINVAL
+    outs[0].d_coalescences = 256                                                  # workspace too small
+    assert B.nh_event_stream(jobs, 1, None, 0, outs, None) == B.NH_ENOMEM
+    assert "workspace" in bd.nh_last_error().decode()
+
+
 @pytest.mark.parametrize("J,Jm,m,nu", [(0, 10, 0.5, 0.1), (10, 0, 0.5, 0.1), (10, 10, 0.0, 0.1), (10, 10, 1.5, 0.1),
                                        (10, 10, 0.5, 0.0), (10, 10, float("nan"), 0.1)])
 def test_implicit_scenario_validation(B, J, Jm, m, nu):

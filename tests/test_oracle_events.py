@@ -45,9 +45,10 @@ def test_stream_is_consistent_with_the_model(k):
     # sorted by (t, origin), each event once
     key = list(zip(ev["t"], ev["origin"]))
     assert all(a < b for a, b in zip(key, key[1:]))
-    # each event is the next event point at its origin after its prior event time
-    for t, prior, origin in zip(ev["t"], ev["prior"], ev["origin"]):
+    # each event is the next event point at its origin after its prior event time, with its outcome
+    for t, prior, origin, outcome in zip(ev["t"], ev["prior"], ev["origin"], ev["outcome"]):
         assert sc.next_event_time(seed, int(origin), float(prior)) == t
+        assert sc.event_outcome(seed, int(origin), float(t)) == outcome
     # coalescences: sorted; the child's arrival and the parent's arrival (or the present) exist
     ck = list(zip(co["t"], co["loc"], co["parent"]))
     assert all(a <= b for a, b in zip(ck, ck[1:]))
