@@ -214,6 +214,7 @@ def main():
         line["host_buffers"] = {"entry": "nh_simulate", "runs": 5, "ms_per_run": host_s * 200.0,
                                 "events_per_s": host_ev / host_s}
         line["poisson_sampler"] = sampler_form(B, W, torch, cfg, stream)
+        line["event_stream"] = stream_form(B, W, torch, cfg, stream)
         line["batched"] = batched_form(args, B, W, torch)
         line["serve"] = served_form(args, W, torch)
     if args.c3:
@@ -246,6 +247,34 @@ def sampler_form(B, W, torch, cfg, stream, steps: int = 10) -> dict:
     el = time.perf_counter() - t0
     return {"workload": wl.name + ", Poisson-count sampler", "steps": steps, "ms_per_step": el * 1e3 / steps,
             "events_per_s": ev / el, "individuals_per_s": steps * n / el}
+
+
+def stream_form(B, W, torch, cfg, stream, reps: int = 5) -> dict:
+    """The event stream of one run of the same torus (nh_event_stream into resident device buffers):
+    the replay of every committed event, the radix sorts and the reduction, timed per call."""
+    dev = torch.device("cuda:0")
+    wl = W.config2()
+    scn = B.Scenario.from_workload(wl)
+    n = len(wl.samples)
+    samples = torch.from_numpy(wl.samples.astype(np.int64)).to(dev)
+    out = torch.empty(n, dtype=torch.int64, device=dev)
+    ws = torch.empty(B.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
+    jobs = [(scn, 42, samples, out, None)]
+    st = B.batch_run(jobs, ws, cfg, stream)[0]
+    co = [torch.empty(n * B.COALESCENCE_DTYPE.itemsize, dtype=torch.uint8, device=dev)]
+    n_ev, n_co = B.event_stream_device(jobs, ws, [None], co, stream)[0]
+    ev = [torch.empty(n_ev * B.EVENT_DTYPE.itemsize, dtype=torch.uint8, device=dev)]
+    B.event_stream_device(jobs, ws, ev, co, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        B.event_stream_device(jobs, ws, ev, co, stream)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    return {"workload": wl.name + ", seed 42", "entry": "nh_event_stream", "reps": reps, "ms_per_stream": el * 1e3,
+            "committed_events_replayed": st["events"], "distinct_events": n_ev, "coalescences": n_co,
+            "distinct_events_per_s": n_ev / el, "records_per_s": (st["events"] + st["merged"]) / el,
+            "simulate_ms": st["device_ms"]}
 
 
 def habitat_form(B, W, torch) -> dict:

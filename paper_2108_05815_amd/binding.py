@@ -393,41 +393,47 @@ def batch_resume(jobs, workspace, config: nh_config | None = None, stream=None):
     return _batch(_lib.nh_batch_resume, "nh_batch_resume", jobs, workspace, config, stream)
 
 
-def event_stream(jobs, workspace, events_cap=None, stream=None):
-    """nh_event_stream for the jobs of the batch run that just finished in `workspace` (the same job
-    tuples as given to batch_run).  events_cap: records of room per job (a list, or one int for all);
-    None counts first and then makes room for every event.  Returns per job (events, coalescences) as
-    numpy arrays of EVENT_DTYPE and COALESCENCE_DTYPE, plus the total counts (n_events may exceed
-    the room given)."""
+def event_stream_device(jobs, workspace, events, coalescences, stream=None):
+    """nh_event_stream into device buffers: events[k] and coalescences[k] are uint8 device tensors
+    (or None for events, to count only) of whole EVENT_DTYPE / COALESCENCE_DTYPE records, the
+    latter with room for job k's samples.  Returns [(n_events, n_coalescences)] per job."""
     import torch
 
     arr = (nh_job * len(jobs))()
     for k, job in enumerate(jobs):
         arr[k] = _job(*job)
-    dev = workspace.device
-    s = stream if stream is not None else torch.cuda.current_stream()
-    if events_cap is None:
-        outs = (nh_stream_out * len(jobs))()
-        co = [torch.empty(max(int(job[2].numel()), 1) * COALESCENCE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
-              for job in jobs]
-        for k in range(len(jobs)):
-            outs[k] = nh_stream_out(None, 0, co[k].data_ptr(), 0, 0)
-        _check(_lib.nh_event_stream(arr, len(jobs), workspace.data_ptr(), workspace.numel(), outs,
-                                    C.c_void_p(s.cuda_stream)), "nh_event_stream")
-        events_cap = [int(o.n_events) for o in outs]
-    if isinstance(events_cap, int):
-        events_cap = [events_cap] * len(jobs)
-    ev = [torch.empty(max(cap, 1) * EVENT_DTYPE.itemsize, dtype=torch.uint8, device=dev) for cap in events_cap]
-    co = [torch.empty(max(int(job[2].numel()), 1) * COALESCENCE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
-          for job in jobs]
     outs = (nh_stream_out * len(jobs))()
     for k in range(len(jobs)):
-        outs[k] = nh_stream_out(ev[k].data_ptr(), events_cap[k], co[k].data_ptr(), 0, 0)
+        ev = events[k]
+        cap = 0 if ev is None else ev.numel() // EVENT_DTYPE.itemsize
+        outs[k] = nh_stream_out(None if ev is None else ev.data_ptr(), cap, coalescences[k].data_ptr(), 0, 0)
+    s = stream if stream is not None else torch.cuda.current_stream()
     _check(_lib.nh_event_stream(arr, len(jobs), workspace.data_ptr(), workspace.numel(), outs,
                                 C.c_void_p(s.cuda_stream)), "nh_event_stream")
+    return [(int(o.n_events), int(o.n_coalescences)) for o in outs]
+
+
+def event_stream(jobs, workspace, events_cap=None, stream=None):
+    """nh_event_stream for the jobs of the batch run that just finished in `workspace` (the same job
+    tuples as given to batch_run).  events_cap: records of room per job (a list, or one int for all);
+    None counts first and then makes room for every event.  Returns per job a dict with the events
+    and coalescences as numpy arrays of EVENT_DTYPE and COALESCENCE_DTYPE and the total counts
+    (n_events may exceed the room given)."""
+    import torch
+
+    dev = workspace.device
+    co = [torch.empty(max(int(job[2].numel()), 1) * COALESCENCE_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+          for job in jobs]
+    if events_cap is None:
+        counts = event_stream_device(jobs, workspace, [None] * len(jobs), co, stream)
+        events_cap = [c[0] for c in counts]
+    if isinstance(events_cap, int):
+        events_cap = [events_cap] * len(jobs)
+    ev = [torch.empty(max(cap, 1) * EVENT_DTYPE.itemsize, dtype=torch.uint8, device=dev)[:cap * EVENT_DTYPE.itemsize]
+          for cap in events_cap]
+    counts = event_stream_device(jobs, workspace, ev, co, stream)
     res = []
-    for k in range(len(jobs)):
-        ne, nc = int(outs[k].n_events), int(outs[k].n_coalescences)
+    for k, (ne, nc) in enumerate(counts):
         e = ev[k].cpu().numpy().view(EVENT_DTYPE)[:min(ne, events_cap[k])]
         c = co[k].cpu().numpy().view(COALESCENCE_DTYPE)[:nc]
         res.append(dict(events=e, coalescences=c, n_events=ne, n_coalescences=nc))
