@@ -1591,51 +1591,67 @@ __global__ void k_stream_count(const JobDev *__restrict__ jobs, Lin lin, uint32_
     n_rec[g] = stream_bad(J, g) ? 0ull : (uint64_t)lin.events[g] + (lin.parent[g] != g ? 1ull : 0ull);
 }
 
-// Replays lineage g's committed events into records off[g] ..; one lane per lineage.
+// Replays lineage g's committed events into records off[g] ..: 8 lanes per
+// lineage with the round kernel's group step (the same bits as its one-lane
+// form), so the longest lineage, which sets the replay time, moves at the
+// tail rate.  The group leader writes the records.
 __global__ void k_stream_replay(const JobDev *__restrict__ jobs, Lin lin, uint32_t n_total,
                                 const uint64_t *__restrict__ off, StreamRecs R, uint32_t *err) {
-    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n_total) return;
-    const uint32_t jb = lin.job[g];
-    const JobDev *J = &jobs[jb];
-    if (stream_bad(J, g)) return;
-    const JobView v = load_view(J);
-    Counters cnt;
-    Pos p = pos_from_loc(v, sample_loc(J, v, J->samples[g - J->lin_base]));
-    double t = next_event_time(v, p.loc, 0.0, err, cnt), prior = 0.0;
-    uint64_t o = off[g];
-    const uint32_t n_ev = lin.events[g];
-    const bool merged = lin.parent[g] != g;
-    for (uint32_t k = 0; k < n_ev; ++k) {
-        if (t < 0.0) { // runaway search (flagged by next_event_time)
-            atomicOr(err, kErrStream);
-            return;
+    const uint32_t lane = lane_id(), gl = lane & (kGroup - 1), grp_base = lane & ~(kGroup - 1);
+    const uint32_t groups = gridDim.x * (blockDim.x / kGroup);
+    // the 8 lanes of a group hold the same g and the same state throughout, so they leave
+    // every loop together
+    for (uint32_t g = (blockIdx.x * blockDim.x + threadIdx.x) / kGroup; g < n_total; g += groups) {
+        const uint32_t jb = lin.job[g];
+        const JobDev *J = &jobs[jb];
+        if (stream_bad(J, g)) continue;
+        const JobView v = load_view(J);
+        Counters cnt;
+        Pos p = pos_from_loc(v, sample_loc(J, v, J->samples[g - J->lin_base]));
+        double t = next_event_time(v, p.loc, 0.0, err, cnt), prior = 0.0;
+        uint64_t o = off[g];
+        const uint32_t n_ev = lin.events[g];
+        const bool merged = lin.parent[g] != g;
+        bool ended = false, bad = false;
+        for (uint32_t k = 0; k < n_ev; ++k) {
+            if (t < 0.0) { // runaway search (flagged by the search)
+                bad = true;
+                break;
+            }
+            const uint32_t from = p.loc;
+            const double te = t;
+            const uint32_t st = group_step<false>(v, p, t, gl, grp_base, cnt);
+            const bool spec = st == kStepSpeciated;
+            if (gl == 0u) {
+                R.t[o] = (uint64_t)__double_as_longlong(te);
+                R.prior[o] = (uint64_t)__double_as_longlong(prior);
+                R.from[o] = from;
+                R.to[o] = spec ? NH_EVENT_SPECIATION : p.loc;
+                R.job[o] = jb;
+            }
+            ++o;
+            if (spec) {
+                // only a representative's last event speciates
+                bad = k + 1 != n_ev || merged;
+                ended = true;
+                break;
+            }
+            if (st == kStepSlow) t = next_event_time_group(v, p.loc, te, gl, grp_base, err, cnt);
+            prior = te;
         }
-        const uint32_t from = p.loc;
-        const bool spec = commit_event<false>(v, p, t, cnt);
-        R.t[o] = (uint64_t)__double_as_longlong(t);
-        R.prior[o] = (uint64_t)__double_as_longlong(prior);
-        R.from[o] = from;
-        R.to[o] = spec ? NH_EVENT_SPECIATION : p.loc;
-        R.job[o] = jb;
-        ++o;
-        if (spec) {
-            // only a representative's last event speciates
-            if (k + 1 != n_ev || merged) atomicOr(err, kErrStream);
-            return;
+        if (!bad && !ended) {
+            // a representative must have ended by speciating
+            bad = !merged || t < 0.0;
+            if (!bad && gl == 0u) {
+                R.t[o] = (uint64_t)__double_as_longlong(t);
+                R.prior[o] = (uint64_t)__double_as_longlong(prior);
+                R.from[o] = p.loc;
+                R.to[o] = kRecMerged;
+                R.job[o] = jb;
+            }
         }
-        prior = t;
-        t = next_event_time(v, p.loc, t, err, cnt);
+        if (bad && gl == 0u) atomicOr(err, kErrStream);
     }
-    if (!merged || t < 0.0) {
-        atomicOr(err, kErrStream); // a representative must have ended by speciating
-        return;
-    }
-    R.t[o] = (uint64_t)__double_as_longlong(t);
-    R.prior[o] = (uint64_t)__double_as_longlong(prior);
-    R.from[o] = p.loc;
-    R.to[o] = kRecMerged;
-    R.job[o] = jb;
 }
 
 __global__ void k_iota(uint32_t *v, uint32_t n) {
@@ -1654,16 +1670,40 @@ __device__ __forceinline__ bool same_event(const StreamRecs &R, uint32_t a, uint
 
 // Over the sorted records: the first copy of an event, and the copies whose prior
 // time differs from the previous copy's (coalescences); counts per job.
+// The per-job counts are added once per wave when the wave's records belong to
+// one job (the usual case: records are sorted by job), so a single-job stream
+// does not funnel every record through one atomic counter.
 __global__ void k_stream_flags(StreamRecs R, const uint32_t *__restrict__ perm, uint32_t n, uint32_t *flag_ev,
                                uint32_t *flag_co, unsigned long long *ev_count, unsigned long long *co_count) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t e = perm[i];
-        const bool first = i == 0 || !same_event(R, perm[i - 1], e);
-        const bool coal = !first && R.prior[perm[i - 1]] != R.prior[e];
-        flag_ev[i] = first;
-        flag_co[i] = coal;
-        if (first) atomicAdd(&ev_count[R.job[e]], 1ull);
-        if (coal) atomicAdd(&co_count[R.job[e]], 1ull);
+    // every lane of a wave runs the same number of iterations, so the ballots see the whole wave
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        const bool valid = i < n;
+        bool first = false, coal = false;
+        uint32_t jb = 0;
+        if (valid) {
+            const uint32_t e = perm[i];
+            first = i == 0 || !same_event(R, perm[i - 1], e);
+            coal = !first && R.prior[perm[i - 1]] != R.prior[e];
+            flag_ev[i] = first;
+            flag_co[i] = coal;
+            jb = R.job[e];
+        }
+        const uint64_t vmask = __ballot(valid);
+        if (vmask == 0) continue;
+        const int lead = __ffsll((unsigned long long)vmask) - 1;
+        const uint32_t jb0 = __shfl(jb, lead, 64);
+        if (__ballot(valid && jb != jb0) == 0) {
+            const unsigned long long ne = (unsigned long long)__popcll(__ballot(first));
+            const unsigned long long nc = (unsigned long long)__popcll(__ballot(coal));
+            if (lane_id() == (uint32_t)lead) {
+                if (ne) atomicAdd(&ev_count[jb0], ne);
+                if (nc) atomicAdd(&co_count[jb0], nc);
+            }
+        } else {
+            if (first) atomicAdd(&ev_count[jb], 1ull);
+            if (coal) atomicAdd(&co_count[jb], 1ull);
+        }
     }
 }
 
@@ -2839,7 +2879,8 @@ int event_stream_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, ui
     if (int rc = S.take(R.job, nr)) return rc;
     // a replay that fails leaves records unwritten: their job index must still be valid
     HIP_TRY(hipMemsetAsync(R.job, 0, sizeof(uint32_t) * nr, stream));
-    k_stream_replay<<<lin_blocks, 256, 0, stream>>>(d_jobs, lin, nt, off, R, err);
+    const uint32_t group_blocks = (uint32_t)std::min<uint64_t>(((uint64_t)nt * kGroup + 255) / 256, 1u << 20);
+    k_stream_replay<<<group_blocks, 256, 0, stream>>>(d_jobs, lin, nt, off, R, err);
     uint32_t *perm_a, *perm_b, *k32_a, *k32_b, *flag_ev, *flag_co, *rank_ev, *rank_co;
     uint64_t *k64_a, *k64_b;
     for (uint32_t **q : {&perm_a, &perm_b, &k32_a, &k32_b, &flag_ev, &flag_co, &rank_ev, &rank_co})
