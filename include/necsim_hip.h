@@ -293,8 +293,10 @@ typedef struct {
  * errors; the workspace is only read.  The library replays each lineage's
  * committed events on the GPU, sorts the records with device radix sorts and
  * reduces them to events and coalescences; it allocates its scratch
- * stream-ordered (about 100 bytes per committed event, below 2^31 of them) and
- * frees it before returning.  Synchronises `stream`.  Runs of the nh_server_*
+ * stream-ordered (about 100 bytes per committed event, below 2^31 of them) from
+ * a library-owned pool per device, which keeps the memory of the largest call
+ * reserved until the process ends, and returns it to that pool before
+ * returning.  Synchronises `stream`.  Runs of the nh_server_*
  * engine have no such workspace.  NH_EINVAL if the workspace holds no finished,
  * error-free run of these jobs or the run committed 2^31 events or more;
  * NH_EDEVICE on a HIP error (an allocation that fails included). */

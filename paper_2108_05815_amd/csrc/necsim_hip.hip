@@ -2742,10 +2742,38 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
     return suspended ? NH_SUSPENDED : NH_OK;
 }
 
+// Library-owned memory pool per device for the event stream's scratch.  It
+// keeps what it has reserved (release threshold: never), so repeated calls
+// reuse the memory of the largest one instead of mapping it again each time;
+// null if the pool cannot be made (the scratch then comes from the device's
+// default pool).
+hipMemPool_t scratch_pool(int device) {
+    static std::mutex mu;
+    static hipMemPool_t pools[64] = {};
+    static bool tried[64] = {};
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0 || device >= 64) return nullptr;
+    if (!tried[device]) {
+        tried[device] = true;
+        hipMemPoolProps props{};
+        props.allocType = hipMemAllocationTypePinned;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = device;
+        hipMemPool_t pool = nullptr;
+        if (hipMemPoolCreate(&pool, &props) == hipSuccess) {
+            uint64_t keep = ~0ull;
+            if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess) pools[device] = pool;
+            else (void)hipMemPoolDestroy(pool);
+        }
+    }
+    return pools[device];
+}
+
 // Stream-ordered scratch allocations of one call, released (stream-ordered)
 // when the call returns.
 struct AsyncScratch {
     hipStream_t stream;
+    hipMemPool_t pool;
     std::vector<void *> held;
     ~AsyncScratch() {
         for (void *q : held) (void)hipFreeAsync(q, stream);
@@ -2753,7 +2781,9 @@ struct AsyncScratch {
     template <typename T>
     int take(T *&out, uint64_t count) {
         void *q = nullptr;
-        HIP_TRY(hipMallocAsync(&q, std::max<uint64_t>(count, 1) * sizeof(T), stream));
+        const uint64_t bytes = std::max<uint64_t>(count, 1) * sizeof(T);
+        if (pool) HIP_TRY(hipMallocFromPoolAsync(&q, bytes, pool, stream));
+        else HIP_TRY(hipMallocAsync(&q, bytes, stream));
         held.push_back(q);
         out = (T *)q;
         return 0;
@@ -2844,7 +2874,9 @@ int event_stream_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, ui
     const Lin lin = lin_view(ws, L);
     const uint32_t nt = (uint32_t)n_total;
     const uint32_t lin_blocks = (nt + 255) / 256;
-    AsyncScratch S{stream, {}};
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    AsyncScratch S{stream, scratch_pool(device), {}};
 
     // Records per lineage and their offsets.
     uint64_t *n_rec = nullptr, *off = nullptr;
