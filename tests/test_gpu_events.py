@@ -128,6 +128,40 @@ def test_event_stream_of_a_mixed_batch_and_a_short_buffer(B, torch_mod):
         assert np.array_equal(got["coalescences"]["t"], ref_co["t"])
 
 
+def test_event_stream_implicit_empty_job_and_reporters(B, torch_mod):
+    """The spatially implicit scenario (with protracted speciation), an empty job between two others,
+    and the speciation events of the stream against the per-sample speciation reporter."""
+    torch = torch_mod
+    dev = torch.device("cuda:0")
+    J, Jm = 200, 2000
+    oimp = oracle.Scenario.implicit(J, Jm, 0.05, 0.01, tau=2.0)
+    gimp = B.Scenario.implicit(J, Jm, 0.05, 0.01, tau=2.0)
+    name, kw, samples, seed = CASES[1]
+    osc, scn = _scenarios(B, kw)
+    samples = _samples(osc, samples)
+    local = np.arange(J, dtype=np.uint64)
+    spec = [(gimp, 3, local), (scn, seed, np.zeros(0, np.uint64)), (scn, seed, samples)]
+    jobs, ws, outs, _ = _run(B, torch, spec)
+    got = B.event_stream(jobs, ws)
+    _assert_same_stream(got[0], *oimp.event_stream(3, local), "implicit")
+    assert got[1]["n_events"] == 0 and got[1]["n_coalescences"] == 0
+    _assert_same_stream(got[2], *osc.event_stream(seed, samples), "after the empty job")
+    # the reporter's speciation event of every sample is one of the stream's speciation events
+    n = len(samples)
+    rep = dict(spec_loc=torch.zeros(n, dtype=torch.int32, device=dev),
+               spec_time=torch.zeros(n, dtype=torch.float64, device=dev))
+    s = torch.from_numpy(samples.astype(np.int64)).to(dev)
+    out = torch.empty(n, dtype=torch.int64, device=dev)
+    ws1 = torch.empty(B.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
+    job = [(scn, seed, s, out, None, rep)]
+    B.batch_run(job, ws1)
+    ev = B.event_stream(job, ws1)[0]["events"]
+    sp = ev["outcome"] == B.NH_EVENT_SPECIATION
+    events = set(zip(ev["origin"][sp].tolist(), ev["t"][sp].tolist()))
+    reported = set(zip(rep["spec_loc"].cpu().numpy().view(np.uint32).tolist(), rep["spec_time"].cpu().numpy().tolist()))
+    assert reported == events
+
+
 def test_event_stream_needs_the_finished_run_of_the_same_jobs(B, torch_mod):
     name, kw, samples, seed = CASES[1]
     osc, scn = _scenarios(B, kw)
