@@ -33,6 +33,12 @@
  *   - Results are a pure function of (scenario, seed, sample id): they do not
  *     depend on the order or partition of the samples, on the batch a job
  *     runs in, or on any tuning parameter in nh_config.
+ *   - Threads: a scenario is immutable after nh_scenario_create, so any
+ *     number of calls may use it at once.  Calls from different host threads
+ *     with different workspaces (and streams) may run concurrently: the
+ *     library's own state is per thread (error message, captured graphs,
+ *     timing events, status word) or guarded by a lock (per-device streams and
+ *     pools).  A workspace, and a server, serves one call at a time.
  */
 #ifndef NECSIM_HIP_H
 #define NECSIM_HIP_H
