@@ -672,3 +672,44 @@ def test_measurement_helpers_report_plausible_rates(B, torch_mod):
     table = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
     g = B.measure_gather(table)
     assert 1e9 < g < 8e12, g
+
+
+def test_concurrent_threads_on_their_own_streams(B, torch_mod):
+    """Two host threads, each with its own stream and workspace, run batches at the same time
+    (ctypes releases the interpreter lock during the library call); every result equals the
+    sequential run's."""
+    import threading
+    torch = torch_mod
+    dev = torch.device("cuda:0")
+    wls = [W.config2(), SMALL[4]]
+    scns = [B.Scenario.from_workload(w) for w in wls]
+    samples = [w.samples if w.samples is not None else np.arange(w.individuals, dtype=np.uint64) for w in wls]
+    ref = [[B.simulate(scns[k], 100 + r, samples[k])[0] for r in range(3)] for k in range(2)]
+    got = [[None] * 3 for _ in range(2)]
+    errors = []
+
+    def worker(k):
+        try:
+            st = torch.cuda.Stream(device=dev)
+            n = len(samples[k])
+            with torch.cuda.stream(st):
+                s = torch.from_numpy(samples[k].astype(np.int64)).to(dev)
+                ws = torch.empty(B.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
+                for r in range(3):
+                    out = torch.empty(n, dtype=torch.int64, device=dev)
+                    B.batch_run([(scns[k], 100 + r, s, out, None)], ws, None, st)
+                    st.synchronize()
+                    got[k][r] = out.cpu().numpy().view(np.uint64)
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=90)
+    assert not any(t.is_alive() for t in threads), "a worker did not finish"
+    assert not errors, errors
+    for k in range(2):
+        for r in range(3):
+            assert np.array_equal(got[k][r], ref[k][r]), (k, r)
