@@ -792,10 +792,19 @@ __device__ __forceinline__ uint32_t swap_neighbour(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1 /* quad_perm [1,0,3,2] */, 0xF, 0xF, true);
 }
 
+// The value of the even (odd) lane of each lane pair, in both lanes: one DPP move.
+__device__ __forceinline__ uint32_t from_even(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xA0 /* quad_perm [0,0,2,2] */, 0xF, 0xF, true);
+}
+__device__ __forceinline__ uint32_t from_odd(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xF5 /* quad_perm [1,1,3,3] */, 0xF, 0xF, true);
+}
+
 // One event of a group plus the first pass of the following event-time
 // search, as straight-line code with a single outcome: kStepOk (the lineage
-// dispersed and t is its next event time), kStepSpeciated (p and t are left
-// at the event) or kStepSlow (the lineage dispersed, t is unchanged, and the
+// dispersed and t is its next event time), kStepSpeciated (t is left at the
+// event; p holds the discarded dispersal, so the caller keeps the event's
+// location) or kStepSlow (the lineage dispersed, t is unchanged, and the
 // search must be finished by next_event_time_group: interval k needs more
 // than four draws, no interval of k .. k+4 holds an event, or t is beyond the
 // 32-bit interval range).  Dispersal and the search are evaluated even when
@@ -819,12 +828,11 @@ __device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double 
     const uint32_t call = gl & 1u;
     uint32_t a0 = p.loc, a1 = (uint32_t)tb, a2 = (uint32_t)(tb >> 32), a3 = (1u << 30) | call;
     philox10(a0, a1, a2, a3, v.key0, v.key1);
-    const uint32_t b0 = swap_neighbour(a0), b1 = swap_neighbour(a1), b2 = swap_neighbour(a2),
-                   b3 = swap_neighbour(a3);
-    const uint64_t wa = ((uint64_t)a1 << 32) | a0, wb = ((uint64_t)a3 << 32) | a2;
-    const uint64_t xa = ((uint64_t)b1 << 32) | b0, xb = ((uint64_t)b3 << 32) | b2;
-    const uint64_t r0 = call ? xa : wa, r1 = call ? xb : wb;
-    const uint64_t r2 = call ? wa : xa, r3 = call ? wb : xb;
+    // even lanes evaluated block 0 (call 0), odd lanes block 1: broadcasts give every lane both
+    const uint64_t r0 = ((uint64_t)from_even(a1) << 32) | from_even(a0);
+    const uint64_t r1 = ((uint64_t)from_even(a3) << 32) | from_even(a2);
+    const uint64_t r2 = ((uint64_t)from_odd(a1) << 32) | from_odd(a0);
+    const uint64_t r3 = ((uint64_t)from_odd(a3) << 32) | from_odd(a2);
     const bool spec = (r0 >> 11) < speciation_threshold<kLds>(v, p, t);
     Pos q = p;
     disperse<kLds>(v, q, r1, r2, r3);
@@ -845,10 +853,7 @@ __device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double 
         const bool counted = (gl == 0u) & !spec & !slow;
         cnt.philox += (gl == 0u ? 2u : 0u) + (counted ? sb : 0u);
         cnt.draws += counted ? sd : 0u;
-        p.x = spec ? p.x : q.x;
-        p.y = spec ? p.y : q.y;
-        p.i = spec ? p.i : q.i;
-        p.loc = spec ? p.loc : q.loc;
+        p = q;
         t = (spec | slow) ? t : e;
         return spec ? kStepSpeciated : (slow ? kStepSlow : kStepOk);
     }
@@ -885,10 +890,7 @@ __device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double 
     cnt.philox += (gl == 0u ? 2u : 0u) + (counted ? ((draws_k + 1u) >> 1) + later : 0u);
     cnt.draws += counted ? draws_k + later : 0u;
 
-    p.x = spec ? p.x : q.x;
-    p.y = spec ? p.y : q.y;
-    p.i = spec ? p.i : q.i;
-    p.loc = spec ? p.loc : q.loc;
+    p = q;
     t = (spec | slow) ? t : (a_hit ? a_e : b_e);
     return spec ? kStepSpeciated : (slow ? kStepSlow : kStepOk);
 }
@@ -1352,6 +1354,7 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
         }
 
         bool finish_live = false, finish_dead = false, speciated = false;
+        uint32_t at = p.loc; // location of the last event (a speciation keeps it)
         // As in the one-lane layout: a drained wave keeps each group in its event loop.  The 8 lanes
         // of a group always agree, so they leave the loop together.
         const bool drained = !q.open && q.chunk_pos >= q.chunk_end;
@@ -1364,6 +1367,7 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
                 uint32_t st;
                 do {
                     ++ev;
+                    at = p.loc;
                     st = group_step<kLds>(v, p, t, gl, grp_base, cnt);
                     if (__builtin_expect(st == kStepSlow, 0)) {
                         t = next_event_time_group(v, p.loc, t, gl, grp_base, err, cnt);
@@ -1382,8 +1386,9 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
         }
         if (finish_dead) {
             if (leader) {
-                lin.species[g] = speciated ? species_of(v, p.loc, t) : 0ull;
-                lin.spec_loc[g] = p.loc;
+                const uint32_t sloc = speciated ? at : p.loc;
+                lin.species[g] = speciated ? species_of(v, sloc, t) : 0ull;
+                lin.spec_loc[g] = sloc;
                 lin.spec_t[g] = t;
                 lin.events[g] += ev;
             }
