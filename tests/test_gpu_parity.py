@@ -629,6 +629,40 @@ def test_protracted_speciation_torus_full_implicit_and_mixed_batch(B, torch_mod)
         assert np.array_equal(outs[k].cpu().numpy().view(np.uint64), alone), k
 
 
+def _rates(w, lam, dt):
+    import copy
+    x = copy.copy(w)
+    x.lam, x.dt = lam, dt
+    x.name = f"{w.name} lambda={lam} dt={dt}"
+    if x.samples is None:
+        x.samples = np.arange(int(x.capacity.astype(np.uint64).sum()), dtype=np.uint64)
+    return x
+
+
+# lambda dt from 1/64 (most searches find no event in the next five intervals) to 64 (every
+# interval needs far more than four draws): both ends leave the group step for its slow search
+RATES = [_rates(SMALL[2], 1.0, 16.0), _rates(SMALL[2], 1.0, 1.0 / 64), _rates(SMALL[2], 64.0, 1.0),
+         _rates(SMALL[4], 4.0, 0.5), _rates(SMALL[0], 0.25, 8.0), _rates(SMALL[3], 2.0, 4.0)]
+
+
+@pytest.mark.parametrize("wl", RATES, ids=[w.name for w in RATES])
+def test_exponential_sampler_rate_and_interval_extremes(B, torch_mod, wl):
+    """The exponential-sum sampler away from lambda dt = 1, bit-exact in both lane layouts."""
+    torch = torch_mod
+    dev = torch.device("cuda:0")
+    say(wl.name, "n =", len(wl.samples))
+    osc = oracle.Scenario(wl.capacity, wl.weights, wl.nu, mode=wl.mode, lam=wl.lam, dt=wl.dt)
+    ref, _, _ = osc.simulate_culled(wl.seeds[0], wl.samples, 2.0 / wl.lam)
+    scn = B.Scenario.from_workload(wl)
+    n = len(wl.samples)
+    s = torch.from_numpy(wl.samples.astype(np.int64)).to(dev)
+    ws = torch.empty(B.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
+    for coop in (1 << 30, 1):
+        out = torch.empty(n, dtype=torch.int64, device=dev)
+        B.batch_run([(scn, wl.seeds[0], s, out, None)], ws, B.make_config(coop_max=coop))
+        assert np.array_equal(out.cpu().numpy().view(np.uint64), ref), coop
+
+
 def test_batch_with_empty_and_duplicate_jobs_and_device_entry_point(B, torch_mod):
     """Empty jobs inside a batch, the same job twice, and nh_simulate_device agree with the plain form."""
     import ctypes as C
