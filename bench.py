@@ -80,6 +80,45 @@ def traffic_from_profile(path: str) -> float | None:
     return float(fields["bytes_per_launch"])
 
 
+def chain_events(ev, co) -> int:
+    """The longest serial chain of the run, in events, read from the event stream: the most events
+    on any sample's path to its speciation.  An event's predecessors are the arrival named by its
+    prior event time and origin, and the arrivals of the lineages that coalesced there during
+    that stay (the coalescences at its origin whose parent arrived at its prior event time); the
+    stream is sorted by time, so one pass computes every event's depth."""
+    from collections import defaultdict
+    t, prior, origin, outcome = (ev["t"].tolist(), ev["t_prior"].tolist(), ev["origin"].tolist(),
+                                 ev["outcome"].tolist())
+    arrival = {(t[i], outcome[i]): i for i in range(len(t)) if outcome[i] != 0xFFFFFFFF}
+    joined = defaultdict(list)
+    for tc, tp, loc in zip(co["t"].tolist(), co["t_parent"].tolist(), co["loc"].tolist()):
+        joined[(loc, tp)].append(tc)
+    depth = [0] * len(t)
+    best = 0
+    for i in range(len(t)):
+        d = depth[arrival[(prior[i], origin[i])]] if prior[i] > 0.0 else 0
+        for tc in joined.get((origin[i], prior[i]), ()):
+            d = max(d, depth[arrival[(tc, origin[i])]])
+        depth[i] = d + 1
+        if outcome[i] == 0xFFFFFFFF:
+            best = max(best, depth[i])
+    return best
+
+
+def latency_bound(B, scn, samples, out, ws, cfg, stream, run_ms: float) -> dict:
+    """The serial bound of the seed-42 simulate: the events on its longest sample path, each waiting
+    on the previous one, times the per-event latency of a lone lineage (measured with the round
+    kernel's group step); frac = bound / the run's stream time."""
+    jobs = [(scn, 42, samples, out, None)]
+    B.batch_run(jobs, ws, cfg, stream)
+    res = B.event_stream(jobs, ws, stream=stream)[0]
+    path = chain_events(res["events"], res["coalescences"])
+    ns = B.measure_event_latency(scn, 42, 20000, stream)
+    bound_ms = path * ns * 1e-6
+    return {"path_events": path, "event_ns": ns, "bound_ms": bound_ms, "run_ms": run_ms, "frac": bound_ms / run_ms,
+            "what": "longest sample path in events x lone-lineage per-event latency, vs the seed-42 run"}
+
+
 def cpu_baseline(wl, budget_s: float) -> dict:
     """The oracle's culled form on whole seeds of the same workload until the budget is spent."""
     import oracle
@@ -155,12 +194,15 @@ def main():
     torch.cuda.synchronize()
     totals = dict(events=0, philox_calls=0, exp_draws=0, round_kernels=0, round_kernel_ms=0.0, richness=0)
     t0 = time.perf_counter()
+    run_ms = []
     for k in range(args.steps):
         st = B.batch_run([(scn, 42 + k, samples, out, rich)], ws, cfg, stream)[0]
+        run_ms.append(st["device_ms"])
         for key in totals:
             totals[key] += st[key]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    latency = latency_bound(B, scn, samples, out, ws, cfg, stream, run_ms[0])
 
     events_per_s = totals["events"] / elapsed
     ops = RL.algorithmic_ops(totals["philox_calls"], totals["exp_draws"], totals["events"])
@@ -205,6 +247,7 @@ def main():
             "ops_per_launch": ops / max(1, totals["round_kernels"]),
             "philox_per_event": totals["philox_calls"] / max(1, totals["events"]),
             "draws_per_event": totals["exp_draws"] / max(1, totals["events"]),
+            "latency": latency,
         },
     }
     if not args.no_extras:

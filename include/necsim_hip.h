@@ -380,6 +380,18 @@ int nh_server_drain(nh_server *server, double timeout_s);
 /* Waits for the server's stream and frees the pool. */
 void nh_server_destroy(nh_server *server);
 
+/* Per-event latency of a lone lineage (the quantity that bounds a run's last
+ * rounds, when a few lineages remain and each event waits on the previous one:
+ * chapter "The Declaration of Independence", each lineage's events form a
+ * sequential chain).  One group of 8 lanes on an otherwise idle device walks
+ * `steps` events of the scenario from sample 0's location with the same group
+ * step as the round kernel (table in LDS where the round kernel would stage
+ * it); *ns_per_event receives the stream time per event.  The walk ignores
+ * speciation.  Synchronises `stream`.  NH_EINVAL for a NULL argument or steps
+ * = 0; NH_EDEVICE on a HIP error. */
+int nh_measure_event_latency(const nh_scenario *scenario, uint64_t seed, uint32_t steps, double *ns_per_event,
+                             void *stream);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char *nh_last_error(void);
 

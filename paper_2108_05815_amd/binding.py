@@ -114,6 +114,8 @@ _lib.nh_batch_resume.restype = C.c_int
 _lib.nh_event_stream.argtypes = [C.POINTER(nh_job), C.c_uint32, C.c_void_p, C.c_uint64, C.POINTER(nh_stream_out),
                                  C.c_void_p]
 _lib.nh_event_stream.restype = C.c_int
+_lib.nh_measure_event_latency.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.POINTER(C.c_double), C.c_void_p]
+_lib.nh_measure_event_latency.restype = C.c_int
 _lib.nh_simulate_device.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
                                     C.POINTER(nh_config), C.POINTER(nh_stats), C.c_void_p]
 _lib.nh_simulate_device.restype = C.c_int
@@ -160,6 +162,7 @@ nh_last_error = _lib.nh_last_error
 nh_version = _lib.nh_version
 nh_measure_mix_peak = _lib.nh_measure_mix_peak
 nh_measure_gather = _lib.nh_measure_gather
+nh_measure_event_latency = _lib.nh_measure_event_latency
 nh_server_bytes = _lib.nh_server_bytes
 nh_server_create = _lib.nh_server_create
 nh_server_submit = _lib.nh_server_submit
@@ -173,7 +176,7 @@ EXPORTED = ["nh_scenario_create", "nh_scenario_create_implicit", "nh_scenario_de
             "nh_simulate_device",
             "nh_simulate", "nh_last_error", "nh_version", "nh_server_bytes", "nh_server_create",
             "nh_server_submit", "nh_server_progress", "nh_server_poll", "nh_server_drain", "nh_server_destroy",
-            "nh_measure_mix_peak", "nh_measure_gather"]
+            "nh_measure_mix_peak", "nh_measure_gather", "nh_measure_event_latency"]
 
 
 class NecsimError(RuntimeError):
@@ -446,6 +449,16 @@ def measure_mix_peak(stream=None) -> float:
     x = C.c_double()
     s = stream if stream is not None else torch.cuda.current_stream()
     _check(_lib.nh_measure_mix_peak(C.byref(x), C.c_void_p(s.cuda_stream)), "nh_measure_mix_peak")
+    return x.value
+
+
+def measure_event_latency(scn, seed: int = 1, steps: int = 20000, stream=None) -> float:
+    """Nanoseconds per event of one lineage walking alone (nh_measure_event_latency)."""
+    import torch
+    x = C.c_double()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(_lib.nh_measure_event_latency(scn.handle, seed, steps, C.byref(x), C.c_void_p(s.cuda_stream)),
+           "nh_measure_event_latency")
     return x.value
 
 

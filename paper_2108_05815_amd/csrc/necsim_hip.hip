@@ -1551,6 +1551,31 @@ __global__ void k_resolve(const JobDev *__restrict__ jobs, JobState *js, Lin lin
     }
 }
 
+// Per-event latency of one lineage on an otherwise idle device: a single group
+// of 8 lanes (one wave, 56 lanes idle, as in the last rounds of a run) walks
+// `steps` events of the round kernel's group step from sample 0's location,
+// the shared table staged in LDS when the round kernel would stage it.  A
+// speciation does not stop the walk (the step has moved the lineage anyway);
+// a runaway search ends it.
+template <bool kLds>
+__global__ void k_event_latency(const JobDev *__restrict__ J, uint32_t steps, uint32_t *err,
+                                unsigned long long *sink) {
+    const JobView v = load_view(J);
+    if (kLds) {
+        for (uint32_t i = threadIdx.x; i < v.n_shared; i += blockDim.x) nh_lds_table[i] = v.table[i];
+        __syncthreads();
+    }
+    const uint32_t lane = lane_id(), gl = lane & (kGroup - 1), grp_base = lane & ~(kGroup - 1);
+    Counters cnt;
+    Pos p = pos_from_loc(v, sample_loc(J, v, 0));
+    double t = next_event_time(v, p.loc, 0.0, err, cnt);
+    for (uint32_t k = 0; k < steps && !(t < 0.0); ++k) {
+        const uint32_t st = group_step<kLds>(v, p, t, gl, grp_base, cnt);
+        if (st == kStepSlow) t = next_event_time_group(v, p.loc, t, gl, grp_base, err, cnt);
+    }
+    if (lane == 0) sink[0] = (unsigned long long)p.loc ^ (unsigned long long)__double_as_longlong(t);
+}
+
 // ---------------------------------------------------------------------------
 // Event stream (sections "Sorting Events using the Water-Level Algorithm" and
 // "Reporting Coalescence Events Independently").  After a completed run each
@@ -3517,3 +3542,54 @@ NH_API int nh_server_drain(nh_server *s, double timeout_s) {
 }
 
 NH_API void nh_server_destroy(nh_server *s) { server_free(s); }
+
+NH_API int nh_measure_event_latency(const nh_scenario *scenario, uint64_t seed, uint32_t steps,
+                                    double *ns_per_event, void *stream_ptr) {
+    if (!scenario || !ns_per_event || steps == 0) return fail(NH_EINVAL, "NULL scenario or output, or no steps");
+    hipStream_t stream = (hipStream_t)stream_ptr;
+    nh_job job{};
+    job.scenario = scenario;
+    job.seed = seed;
+    JobDev hd;
+    job_descriptor(hd, job, nullptr, nullptr, 0, 64, 0);
+    const bool lds = scenario->mode == NH_DISPERSAL_SHARED && scenario->n_shared <= kLdsTableMax;
+    const size_t lds_bytes = lds ? sizeof(uint4) * scenario->n_shared : 0;
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    AsyncScratch S{stream, nullptr, {}};
+    JobDev *d_job = nullptr;
+    uint32_t *err = nullptr;
+    unsigned long long *sink = nullptr;
+    if (int rc = S.take(d_job, 1)) return rc;
+    if (int rc = S.take(err, 1)) return rc;
+    if (int rc = S.take(sink, 1)) return rc;
+    HIP_TRY(hipMemcpyAsync(d_job, &hd, sizeof hd, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemsetAsync(err, 0, sizeof(uint32_t), stream));
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{a, b};
+    auto launch = [&](uint32_t n) {
+        if (lds) k_event_latency<true><<<1, kGroup, lds_bytes, stream>>>(d_job, n, err, sink);
+        else k_event_latency<false><<<1, kGroup, 0, stream>>>(d_job, n, err, sink);
+    };
+    launch(std::min<uint32_t>(steps, 256)); // warm-up
+    HIP_TRY(hipEventRecord(a, stream));
+    launch(steps);
+    HIP_TRY(hipEventRecord(b, stream));
+    HIP_TRY(hipGetLastError());
+    uint32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, err, sizeof herr, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (herr) return fail(NH_EDEVICE, "the latency walk ran away (flags %#x)", herr);
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, a, b));
+    *ns_per_event = (double)ms * 1e6 / steps;
+    return NH_OK;
+}

@@ -706,6 +706,11 @@ def test_measurement_helpers_report_plausible_rates(B, torch_mod):
     table = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
     g = B.measure_gather(table)
     assert 1e9 < g < 8e12, g
+    # a lone lineage's event: two Philox blocks, a logarithm and the dispersal in sequence, each
+    # hundreds of clocks at 2.4 GHz; neither the LDS-staged nor the global-table form leaves that range
+    for scn in (B.Scenario.from_workload(W.config2()), B.Scenario.from_workload(SMALL[4])):
+        ns = B.measure_event_latency(scn, 1, 4000)
+        assert 100.0 < ns < 20000.0, ns
 
 
 def test_concurrent_threads_on_their_own_streams(B, torch_mod):

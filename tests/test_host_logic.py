@@ -87,3 +87,25 @@ def test_traffic_record_goes_stale_with_the_kernel(tmp_path):
     stale.write_text("kernel_source_sha256: 00\nbytes_per_launch: 1\n")
     assert bench.traffic_from_profile(str(stale)) is None
     assert bench.traffic_from_profile(str(tmp_path / "missing.txt")) is None
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_chain_events_is_the_longest_sample_path(case):
+    """bench.py's serial-chain length, read from an event stream, equals the most events any
+    sample's lineage goes through (the oracle tracing each sample alone)."""
+    import numpy as np
+    import bench
+    import oracle
+    from paper_2108_05815_amd import workloads as W
+    cap, w, nu, seed = [(np.ones((16, 16), np.uint32), W.gaussian_kernel(1.5, 3), 0.02, 3),
+                        (np.full((10, 10), 2, np.uint32), np.ones((3, 3)), 0.01, 5),
+                        (np.array([[50]], np.uint32), np.ones((1, 1)), 0.01, 7)][case]
+    sc = oracle.Scenario(cap, w, nu)
+    s = np.arange(sc.individuals, dtype=np.uint64)
+    ev, co = sc.event_stream(seed, s)
+    e = np.zeros(len(ev["t"]), dtype=[("t", "<f8"), ("t_prior", "<f8"), ("origin", "<u4"), ("outcome", "<u4")])
+    e["t"], e["t_prior"], e["origin"], e["outcome"] = ev["t"], ev["prior"], ev["origin"], ev["outcome"]
+    c = np.zeros(len(co["t"]), dtype=[("t", "<f8"), ("t_parent", "<f8"), ("loc", "<u4"), ("reserved", "<u4")])
+    c["t"], c["t_parent"], c["loc"] = co["t"], co["parent"], co["loc"]
+    _, _, events = sc.simulate_naive(seed, s)
+    assert bench.chain_events(e, c) == int(events.max())
