@@ -484,11 +484,29 @@ __device__ __forceinline__ uint64_t species_of(const JobView &v, uint32_t loc, d
     return ((uint64_t)s1 << 32) | s0;
 }
 
-// Dispersal from the event draws: the alias column from r1, the alias coin
-// from r2, the torus offset of the chosen entry, and the deme index from r3.
-// A table staged in LDS is always the shared one.
+// The alias-table row of the lineage's cell: its first and one-past-last
+// entries.  The row pointers depend on the cell alone, so a caller issues this
+// before the event's hash and the loads overlap it: they are unconditional
+// (every scenario has row pointers; a shared table is the single row {0, n},
+// also read by the spatially implicit scenario, whose dispersal ignores it),
+// and a scheduling barrier keeps them ahead of the hash, whose first use of
+// them comes after it.
 template <bool kLds>
-__device__ __forceinline__ void disperse(const JobView &v, Pos &p, uint64_t r1, uint64_t r2, uint64_t r3) {
+__device__ __forceinline__ uint2 table_row(const JobView &v, const Pos &p) {
+    if (kLds) return make_uint2(0u, v.n_shared);
+    const uint32_t cell = v.mode == NH_DISPERSAL_PER_DEME ? p.y * v.W + p.x : 0u;
+    const uint2 row = make_uint2(v.row_ptr[cell], v.row_ptr[cell + 1]);
+    __builtin_amdgcn_sched_barrier(0);
+    return row;
+}
+
+// Dispersal from the event draws: the alias column from r1, the alias coin
+// from r2, the torus offset of the chosen entry, and the deme index from r3;
+// row is table_row of the lineage's cell (first and one-past-last entry).  A
+// table staged in LDS is always the shared one.
+template <bool kLds>
+__device__ __forceinline__ void disperse(const JobView &v, Pos &p, uint64_t r1, uint64_t r2, uint64_t r3,
+                                         uint2 row) {
     if (!kLds && v.mode == kModeImplicit) {
         // Spatially implicit (background section "Spatially Implicit"): cell 0 is the local
         // community, cell 1 the metacommunity; a local event migrates with probability m (r1),
@@ -499,15 +517,7 @@ __device__ __forceinline__ void disperse(const JobView &v, Pos &p, uint64_t r1, 
         p.loc = target * v.cmax + p.i;
         return;
     }
-    uint32_t first, n;
-    if (kLds || v.mode == NH_DISPERSAL_SHARED) {
-        first = 0;
-        n = v.n_shared;
-    } else {
-        const uint32_t cell = p.y * v.W + p.x;
-        first = v.row_ptr[cell];
-        n = v.row_ptr[cell + 1] - first;
-    }
+    const uint32_t first = row.x, n = row.y - row.x;
     const uint32_t col = mulhi_index(r1, n);
     const uint4 ent = kLds ? nh_lds_table[first + col] : v.table[first + col];
     const uint64_t thresh = ((uint64_t)ent.y << 32) | ent.x;
@@ -534,6 +544,7 @@ __device__ __forceinline__ void disperse(const JobView &v, Pos &p, uint64_t r1, 
 // Returns true on speciation.
 template <bool kLds = false>
 __device__ __forceinline__ bool commit_event(const JobView &v, Pos &p, double t, Counters &cnt) {
+    const uint2 row = table_row<kLds>(v, p);
     const uint64_t tb = (uint64_t)__double_as_longlong(t);
     const uint32_t tlo = (uint32_t)tb, thi = (uint32_t)(tb >> 32);
     // Both blocks side by side (two independent chains in one lane), block 1
@@ -548,7 +559,7 @@ __device__ __forceinline__ bool commit_event(const JobView &v, Pos &p, double t,
     const uint64_t r3 = ((uint64_t)b3 << 32) | b2;
     cnt.philox += 2;
     if (__builtin_expect((r0 >> 11) < speciation_threshold<kLds>(v, p, t), 0)) return true;
-    disperse<kLds>(v, p, r1, r2, r3);
+    disperse<kLds>(v, p, r1, r2, r3, row);
     return false;
 }
 
@@ -824,6 +835,7 @@ __device__ __forceinline__ uint32_t group_sum8(uint32_t x) {
 template <bool kLds>
 __device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double &t, uint32_t gl, uint32_t grp_base,
                                                Counters &cnt) {
+    const uint2 row = table_row<kLds>(v, p);
     const uint64_t tb = (uint64_t)__double_as_longlong(t);
     const uint32_t call = gl & 1u;
     uint32_t a0 = p.loc, a1 = (uint32_t)tb, a2 = (uint32_t)(tb >> 32), a3 = (1u << 30) | call;
@@ -835,7 +847,7 @@ __device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double 
     const uint64_t r3 = ((uint64_t)from_odd(a3) << 32) | from_odd(a2);
     const bool spec = (r0 >> 11) < speciation_threshold<kLds>(v, p, t);
     Pos q = p;
-    disperse<kLds>(v, q, r1, r2, r3);
+    disperse<kLds>(v, q, r1, r2, r3, row);
 
     const double kf = floor(t * v.inv_dt);
     const bool wide = !(kf < 2147483648.0);
@@ -2330,9 +2342,13 @@ NH_API int nh_scenario_create(const nh_habitat *habitat, const nh_dispersal *dis
         tb.build(-1, host.data());
         s->n_shared = n;
         s->n_entries = n;
-        if (hipMallocAsync((void **)&s->d_table, sizeof(uint4) * n, ts) != hipSuccess)
+        // the shared table is one row {0, n} of row pointers, so every scenario has them
+        const uint32_t row[2] = {0u, n};
+        if (hipMallocAsync((void **)&s->d_table, sizeof(uint4) * n, ts) != hipSuccess ||
+            hipMallocAsync((void **)&s->d_row_ptr, sizeof row, ts) != hipSuccess)
             return bail(fail(NH_ENOMEM, "device table allocation failed"));
         if (hipMemcpyAsync(s->d_table, host.data(), sizeof(uint4) * n, hipMemcpyHostToDevice, ts) != hipSuccess ||
+            hipMemcpyAsync(s->d_row_ptr, row, sizeof row, hipMemcpyHostToDevice, ts) != hipSuccess ||
             hipStreamSynchronize(ts) != hipSuccess)
             return bail(fail(NH_EDEVICE, "table upload failed"));
     } else {
@@ -2405,7 +2421,8 @@ NH_API int nh_scenario_create(const nh_habitat *habitat, const nh_dispersal *dis
             hipSuccess ||
         hipStreamSynchronize(ts) != hipSuccess)
         return bail(fail(NH_EDEVICE, "capacity upload failed"));
-    s->table_bytes = sizeof(uint4) * s->n_entries + (s->d_row_ptr ? 4 * (cells + 1) : 0) + 4 * cells + 8 * (cells + 1);
+    s->table_bytes = sizeof(uint4) * s->n_entries + (s->mode == NH_DISPERSAL_PER_DEME ? 4 * (cells + 1) : 8) +
+                     4 * cells + 8 * (cells + 1);
     *out = s;
     return NH_OK;
 }
