@@ -832,10 +832,12 @@ __device__ __forceinline__ uint32_t group_sum8(uint32_t x) {
     return x + half_mirror(x);
 }
 
+// row is table_row of p on entry and of the moved p on return: the next
+// event's row pointers are requested as soon as the dispersal is known, so
+// their loads overlap the search and the next event's hash.
 template <bool kLds>
-__device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double &t, uint32_t gl, uint32_t grp_base,
-                                               Counters &cnt) {
-    const uint2 row = table_row<kLds>(v, p);
+__device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double &t, uint2 &row, uint32_t gl,
+                                               uint32_t grp_base, Counters &cnt) {
     const uint64_t tb = (uint64_t)__double_as_longlong(t);
     const uint32_t call = gl & 1u;
     uint32_t a0 = p.loc, a1 = (uint32_t)tb, a2 = (uint32_t)(tb >> 32), a3 = (1u << 30) | call;
@@ -848,6 +850,7 @@ __device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double 
     const bool spec = (r0 >> 11) < speciation_threshold<kLds>(v, p, t);
     Pos q = p;
     disperse<kLds>(v, q, r1, r2, r3, row);
+    row = table_row<kLds>(v, q);
 
     const double kf = floor(t * v.inv_dt);
     const bool wide = !(kf < 2147483648.0);
@@ -1377,10 +1380,11 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
                 // The rare slow search is finished inside the iteration: a group that left the loop
                 // for it would wait there until every other group of the wave had left the loop too.
                 uint32_t st;
+                uint2 row = table_row<kLds>(v, p);
                 do {
                     ++ev;
                     at = p.loc;
-                    st = group_step<kLds>(v, p, t, gl, grp_base, cnt);
+                    st = group_step<kLds>(v, p, t, row, gl, grp_base, cnt);
                     if (__builtin_expect(st == kStepSlow, 0)) {
                         t = next_event_time_group(v, p.loc, t, gl, grp_base, err, cnt);
                         st = t < 0.0 ? kStepSlow : kStepOk; // kStepSlow now marks a runaway search
@@ -1581,8 +1585,9 @@ __global__ void k_event_latency(const JobDev *__restrict__ J, uint32_t steps, ui
     Counters cnt;
     Pos p = pos_from_loc(v, sample_loc(J, v, 0));
     double t = next_event_time(v, p.loc, 0.0, err, cnt);
+    uint2 row = table_row<kLds>(v, p);
     for (uint32_t k = 0; k < steps && !(t < 0.0); ++k) {
-        const uint32_t st = group_step<kLds>(v, p, t, gl, grp_base, cnt);
+        const uint32_t st = group_step<kLds>(v, p, t, row, gl, grp_base, cnt);
         if (st == kStepSlow) t = next_event_time_group(v, p.loc, t, gl, grp_base, err, cnt);
     }
     if (lane == 0) sink[0] = (unsigned long long)p.loc ^ (unsigned long long)__double_as_longlong(t);
@@ -1655,6 +1660,7 @@ __global__ void k_stream_replay(const JobDev *__restrict__ jobs, Lin lin, uint32
         const uint32_t n_ev = lin.events[g];
         const bool merged = lin.parent[g] != g;
         bool ended = false, bad = false;
+        uint2 row = table_row<false>(v, p);
         for (uint32_t k = 0; k < n_ev; ++k) {
             if (t < 0.0) { // runaway search (flagged by the search)
                 bad = true;
@@ -1662,7 +1668,7 @@ __global__ void k_stream_replay(const JobDev *__restrict__ jobs, Lin lin, uint32
             }
             const uint32_t from = p.loc;
             const double te = t;
-            const uint32_t st = group_step<false>(v, p, t, gl, grp_base, cnt);
+            const uint32_t st = group_step<false>(v, p, t, row, gl, grp_base, cnt);
             const bool spec = st == kStepSpeciated;
             if (gl == 0u) {
                 R.t[o] = (uint64_t)__double_as_longlong(te);
