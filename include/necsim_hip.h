@@ -295,8 +295,9 @@ typedef struct {
 
 /* The event stream of every job of the batch run that just finished in
  * d_workspace: jobs must be the run's own jobs (same scenarios, seeds and sample
- * buffers, all still alive), the run complete (not suspended) and free of
- * errors; the workspace is only read.  The library replays each lineage's
+ * buffers, all still alive and the samples unchanged, since the replay reads
+ * them again), the run complete (not suspended) and free of errors; the
+ * workspace is only read.  The library replays each lineage's
  * committed events on the GPU, sorts the records with device radix sorts and
  * reduces them to events and coalescences; it allocates its scratch
  * stream-ordered (about 100 bytes per committed event, below 2^31 of them) from
