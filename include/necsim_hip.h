@@ -393,6 +393,43 @@ void nh_server_destroy(nh_server *server);
 int nh_measure_event_latency(const nh_scenario *scenario, uint64_t seed, uint32_t steps, double *ns_per_event,
                              void *stream);
 
+/* Device evaluation of the path's primitives on given inputs, for unit tests
+ * of the kernels' building blocks against a host implementation (chapter "The
+ * Declaration of Independence": priming, exponential waiting times, the event
+ * summary).  For item i < n (device arrays; each pair may be NULL):
+ *   d_ctr[4i..4i+3] -> d_philox_out[4i..4i+3]: the Philox4x32-10 block of that
+ *     counter under key (seed low word, seed high word);
+ *   d_r[i] -> d_log_out[i]: log(((r >> 11) + 1) 2^-53), the logarithm the
+ *     event-time search applies to a draw;
+ *   (d_loc[i], d_t[i]) -> d_next_out[i]: the next event time after t at loc
+ *     (one-lane search); d_next_group_out[i]: the same by the 8-lane group
+ *     search; d_outcome_out[i]: the outcome of an event at (loc, t), the new
+ *     location or NH_EVENT_SPECIATION; (d_step_loc_out[i], d_step_t_out[i]):
+ *     one group step from (loc, t), the new location and its next event time,
+ *     or (NH_EVENT_SPECIATION, t).
+ * Locations are loc32 of the scenario; an item whose location is no slot of
+ * the scenario, or whose time is not finite, non-negative and below 2^40, gets
+ * NaN or 0xFFFFFFFF outputs.  use_lds stages a small shared table in LDS as the
+ * single-job round kernel does.  Synchronises `stream`.  NH_EINVAL for a NULL
+ * scenario or io, unpaired arrays, or event outputs without d_loc and d_t;
+ * NH_EDEVICE on a HIP error or a search that ran away. */
+typedef struct {
+    const uint32_t *d_ctr;
+    uint32_t *d_philox_out;
+    const uint64_t *d_r;
+    double *d_log_out;
+    const uint32_t *d_loc;
+    const double *d_t;
+    double *d_next_out;
+    double *d_next_group_out;
+    uint32_t *d_outcome_out;
+    uint32_t *d_step_loc_out;
+    double *d_step_t_out;
+} nh_primitive_io;
+
+int nh_eval_primitives(const nh_scenario *scenario, uint64_t seed, uint64_t n, const nh_primitive_io *io,
+                       uint32_t use_lds, void *stream);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char *nh_last_error(void);
 

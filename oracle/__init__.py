@@ -69,6 +69,17 @@ def _load():
         lib.or_sample_location.restype = C.c_uint32
         lib.or_event_outcome.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_double]
         lib.or_event_outcome.restype = C.c_uint32
+        lib.or_philox_array.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.c_uint64,
+                                        C.POINTER(C.c_uint32)]
+        lib.or_philox_array.restype = None
+        lib.or_log_u53o_array.argtypes = [C.POINTER(C.c_uint64), C.c_uint64, C.POINTER(C.c_double)]
+        lib.or_log_u53o_array.restype = None
+        lib.or_next_event_time_array.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_uint32),
+                                                 C.POINTER(C.c_double), C.c_uint64, C.POINTER(C.c_double)]
+        lib.or_next_event_time_array.restype = None
+        lib.or_event_outcome_array.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_uint32), C.POINTER(C.c_double),
+                                               C.c_uint64, C.POINTER(C.c_uint32)]
+        lib.or_event_outcome_array.restype = None
         lib.or_scenario_create_implicit.argtypes = [C.c_uint32, C.c_uint32, C.c_double, C.c_double, C.c_double,
                                                     C.c_double, C.POINTER(C.c_void_p)]
         lib.or_scenario_create_implicit.restype = C.c_int
@@ -112,6 +123,25 @@ def philox4x32_10(ctr, key) -> np.ndarray:
     k = np.ascontiguousarray(key, dtype=np.uint32)
     out = np.zeros(4, dtype=np.uint32)
     lib.or_philox4x32_10(_ptr(c, C.c_uint32), _ptr(k, C.c_uint32), _ptr(out, C.c_uint32))
+    return out
+
+
+def philox_array(ctr, key) -> np.ndarray:
+    """Philox4x32-10 of every counter row (n x 4 u32) under one key (2 u32)."""
+    lib = _load()
+    c = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros_like(c)
+    lib.or_philox_array(_ptr(c, C.c_uint32), _ptr(k, C.c_uint32), len(c), _ptr(out, C.c_uint32))
+    return out
+
+
+def log_u53o_array(r) -> np.ndarray:
+    """log(((r >> 11) + 1) 2^-53) for every u64 draw r, as the event-time search takes it."""
+    lib = _load()
+    x = np.ascontiguousarray(r, dtype=np.uint64)
+    out = np.zeros(len(x), dtype=np.float64)
+    lib.or_log_u53o_array(_ptr(x, C.c_uint64), len(x), _ptr(out, C.c_double))
     return out
 
 
@@ -266,6 +296,22 @@ class Scenario:
         if rc != 0:
             raise ValueError(f"simulate_culled failed ({rc})")
         return sp, int(ev.value), int(rounds.value)
+
+    def next_event_time_array(self, seed: int, loc, t) -> np.ndarray:
+        l = np.ascontiguousarray(loc, dtype=np.uint32)
+        x = np.ascontiguousarray(t, dtype=np.float64)
+        out = np.zeros(len(l), dtype=np.float64)
+        self._lib.or_next_event_time_array(self._h, seed, _ptr(l, C.c_uint32), _ptr(x, C.c_double), len(l),
+                                           _ptr(out, C.c_double))
+        return out
+
+    def event_outcome_array(self, seed: int, loc, t) -> np.ndarray:
+        l = np.ascontiguousarray(loc, dtype=np.uint32)
+        x = np.ascontiguousarray(t, dtype=np.float64)
+        out = np.zeros(len(l), dtype=np.uint32)
+        self._lib.or_event_outcome_array(self._h, seed, _ptr(l, C.c_uint32), _ptr(x, C.c_double), len(l),
+                                         _ptr(out, C.c_uint32))
+        return out
 
     def event_outcome(self, seed: int, loc: int, t: float) -> int:
         """Outcome of the event at (loc, t): the new location, or EVENT_SPECIATION."""

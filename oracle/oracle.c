@@ -845,3 +845,25 @@ OR_EXPORT uint32_t or_event_outcome(or_scenario *s, uint64_t seed, uint32_t loc,
     uint64_t sp = 0;
     return commit_event(s, seed, &loc, t, &sp, NULL, NULL) ? OR_EVENT_SPECIATION : loc;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Array forms of the primitives, for comparing many inputs at once (test    */
+/* infrastructure; each item is the single-item function above).            */
+/* ------------------------------------------------------------------------- */
+OR_EXPORT void or_philox_array(const uint32_t *ctr, const uint32_t key[2], uint64_t n, uint32_t *out) {
+    for (uint64_t i = 0; i < n; ++i) or_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
+OR_EXPORT void or_log_u53o_array(const uint64_t *r, uint64_t n, double *out) {
+    for (uint64_t i = 0; i < n; ++i) out[i] = or_log(u53_open0(r[i]));
+}
+
+OR_EXPORT void or_next_event_time_array(const or_scenario *s, uint64_t seed, const uint32_t *loc, const double *t,
+                                        uint64_t n, double *out) {
+    for (uint64_t i = 0; i < n; ++i) out[i] = or_next_event_time(s, seed, loc[i], t[i]);
+}
+
+OR_EXPORT void or_event_outcome_array(or_scenario *s, uint64_t seed, const uint32_t *loc, const double *t, uint64_t n,
+                                      uint32_t *out) {
+    for (uint64_t i = 0; i < n; ++i) out[i] = or_event_outcome(s, seed, loc[i], t[i]);
+}

@@ -77,6 +77,13 @@ COALESCENCE_DTYPE = np.dtype([("t", "<f8"), ("t_parent", "<f8"), ("loc", "<u4"),
 NH_EVENT_SPECIATION = 0xFFFFFFFF
 
 
+class nh_primitive_io(C.Structure):
+    _fields_ = [("d_ctr", C.c_void_p), ("d_philox_out", C.c_void_p), ("d_r", C.c_void_p), ("d_log_out", C.c_void_p),
+                ("d_loc", C.c_void_p), ("d_t", C.c_void_p), ("d_next_out", C.c_void_p),
+                ("d_next_group_out", C.c_void_p), ("d_outcome_out", C.c_void_p), ("d_step_loc_out", C.c_void_p),
+                ("d_step_t_out", C.c_void_p)]
+
+
 class nh_server_config(C.Structure):
     _fields_ = [("lineage_capacity", C.c_uint64), ("max_jobs", C.c_uint32), ("lookahead", C.c_uint32),
                 ("cfg", nh_config)]
@@ -116,6 +123,9 @@ _lib.nh_event_stream.argtypes = [C.POINTER(nh_job), C.c_uint32, C.c_void_p, C.c_
 _lib.nh_event_stream.restype = C.c_int
 _lib.nh_measure_event_latency.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.POINTER(C.c_double), C.c_void_p]
 _lib.nh_measure_event_latency.restype = C.c_int
+_lib.nh_eval_primitives.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.POINTER(nh_primitive_io), C.c_uint32,
+                                    C.c_void_p]
+_lib.nh_eval_primitives.restype = C.c_int
 _lib.nh_simulate_device.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
                                     C.POINTER(nh_config), C.POINTER(nh_stats), C.c_void_p]
 _lib.nh_simulate_device.restype = C.c_int
@@ -163,6 +173,7 @@ nh_version = _lib.nh_version
 nh_measure_mix_peak = _lib.nh_measure_mix_peak
 nh_measure_gather = _lib.nh_measure_gather
 nh_measure_event_latency = _lib.nh_measure_event_latency
+nh_eval_primitives = _lib.nh_eval_primitives
 nh_server_bytes = _lib.nh_server_bytes
 nh_server_create = _lib.nh_server_create
 nh_server_submit = _lib.nh_server_submit
@@ -176,7 +187,7 @@ EXPORTED = ["nh_scenario_create", "nh_scenario_create_implicit", "nh_scenario_de
             "nh_simulate_device",
             "nh_simulate", "nh_last_error", "nh_version", "nh_server_bytes", "nh_server_create",
             "nh_server_submit", "nh_server_progress", "nh_server_poll", "nh_server_drain", "nh_server_destroy",
-            "nh_measure_mix_peak", "nh_measure_gather", "nh_measure_event_latency"]
+            "nh_measure_mix_peak", "nh_measure_gather", "nh_measure_event_latency", "nh_eval_primitives"]
 
 
 class NecsimError(RuntimeError):
@@ -460,6 +471,58 @@ def measure_event_latency(scn, seed: int = 1, steps: int = 20000, stream=None) -
     _check(_lib.nh_measure_event_latency(scn.handle, seed, steps, C.byref(x), C.c_void_p(s.cuda_stream)),
            "nh_measure_event_latency")
     return x.value
+
+
+def eval_primitives(scn, seed: int, ctr=None, r=None, loc=None, t=None, use_lds: bool = True, stream=None) -> dict:
+    """nh_eval_primitives on host arrays (copied to the device and back): Philox blocks of ctr
+    (n x 4 u32), logarithms of the draws r (u64), and for the (loc, t) pairs the one-lane and group
+    next event times, the event outcomes and one group step each."""
+    import torch
+    dev = torch.device("cuda:0")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    io = nh_primitive_io()
+    keep, out = [], {}
+
+    def put(a, dtype):
+        x = torch.from_numpy(np.ascontiguousarray(a).view(dtype)).to(dev)
+        keep.append(x)
+        return x.data_ptr()
+
+    def make(name, count, dtype):
+        x = torch.empty(max(count, 1), dtype=dtype, device=dev)
+        out[name] = x
+        return x.data_ptr()
+
+    n = 0
+    if ctr is not None:
+        c = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+        n = max(n, len(c))
+        io.d_ctr, io.d_philox_out = put(c.reshape(-1).view(np.int32), np.int32), make("philox", 4 * len(c), torch.int32)
+    if r is not None:
+        rr = np.ascontiguousarray(r, dtype=np.uint64)
+        n = max(n, len(rr))
+        io.d_r, io.d_log_out = put(rr.view(np.int64), np.int64), make("log", len(rr), torch.float64)
+    if loc is not None:
+        l = np.ascontiguousarray(loc, dtype=np.uint32)
+        n = max(n, len(l))
+        io.d_loc, io.d_t = put(l.view(np.int32), np.int32), put(np.ascontiguousarray(t, dtype=np.float64), np.float64)
+        io.d_next_out = make("next", len(l), torch.float64)
+        io.d_next_group_out = make("next_group", len(l), torch.float64)
+        io.d_outcome_out = make("outcome", len(l), torch.int32)
+        io.d_step_loc_out = make("step_loc", len(l), torch.int32)
+        io.d_step_t_out = make("step_t", len(l), torch.float64)
+    lens = [len(x) for x in (ctr if ctr is None else np.asarray(ctr).reshape(-1, 4), r, loc) if x is not None]
+    if len(set(lens)) > 1:
+        raise ValueError("ctr, r and loc must have the same number of items")
+    _check(_lib.nh_eval_primitives(scn.handle, seed, n, C.byref(io), int(use_lds), C.c_void_p(s.cuda_stream)),
+           "nh_eval_primitives")
+    res = {}
+    for name, x in out.items():
+        a = x.cpu().numpy()
+        if name in ("philox", "outcome", "step_loc"):
+            a = a.view(np.uint32)
+        res[name] = a.reshape(-1, 4)[:n] if name == "philox" else a[:n]
+    return res
 
 
 def measure_gather(table, stream=None) -> float:

@@ -1593,6 +1593,72 @@ __global__ void k_event_latency(const JobDev *__restrict__ J, uint32_t steps, ui
     if (lane == 0) sink[0] = (unsigned long long)p.loc ^ (unsigned long long)__double_as_longlong(t);
 }
 
+// The path's primitives on given inputs, for device-level unit tests: 8 lanes
+// per item (the group forms need a whole group; lane 0 runs the one-lane
+// forms and writes).  An item whose location is not a slot of the scenario, or
+// whose time is not a finite non-negative number below 2^40, gets NaN and
+// 0xFFFFFFFF outputs and reads no table.
+template <bool kLds>
+__global__ void k_primitives(const JobDev *__restrict__ J, uint64_t n, nh_primitive_io io, uint32_t *err) {
+    const JobView v = load_view(J);
+    if (kLds) {
+        for (uint32_t i = threadIdx.x; i < v.n_shared; i += blockDim.x) nh_lds_table[i] = v.table[i];
+        __syncthreads();
+    }
+    const uint32_t lane = lane_id(), gl = lane & (kGroup - 1), grp_base = lane & ~(kGroup - 1);
+    const uint64_t groups = (uint64_t)gridDim.x * (blockDim.x / kGroup);
+    // the 8 lanes of a group hold the same item, so they take every branch together
+    for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroup; i < n; i += groups) {
+        if (io.d_ctr && io.d_philox_out && gl == 0u) {
+            uint32_t c0 = io.d_ctr[4 * i], c1 = io.d_ctr[4 * i + 1], c2 = io.d_ctr[4 * i + 2], c3 = io.d_ctr[4 * i + 3];
+            philox10(c0, c1, c2, c3, v.key0, v.key1);
+            io.d_philox_out[4 * i] = c0;
+            io.d_philox_out[4 * i + 1] = c1;
+            io.d_philox_out[4 * i + 2] = c2;
+            io.d_philox_out[4 * i + 3] = c3;
+        }
+        if (io.d_r && io.d_log_out && gl == 0u) io.d_log_out[i] = log_u53o(io.d_r[i]);
+        if (!io.d_loc || !io.d_t) continue;
+        const uint32_t loc = io.d_loc[i];
+        const double t = io.d_t[i];
+        const uint32_t cell = loc / v.cmax;
+        const bool ok = cell < v.W * v.H && loc - cell * v.cmax < J->cap[cell] && t >= 0.0 && t < 0x1p40;
+        if (!ok) {
+            if (gl == 0u) {
+                if (io.d_next_out) io.d_next_out[i] = __builtin_nan("");
+                if (io.d_next_group_out) io.d_next_group_out[i] = __builtin_nan("");
+                if (io.d_outcome_out) io.d_outcome_out[i] = 0xFFFFFFFFu;
+                if (io.d_step_loc_out) io.d_step_loc_out[i] = 0xFFFFFFFFu;
+                if (io.d_step_t_out) io.d_step_t_out[i] = __builtin_nan("");
+            }
+            continue;
+        }
+        Counters cnt;
+        if (io.d_next_out && gl == 0u) io.d_next_out[i] = next_event_time(v, loc, t, err, cnt);
+        if (io.d_next_group_out) {
+            const double e = next_event_time_group(v, loc, t, gl, grp_base, err, cnt);
+            if (gl == 0u) io.d_next_group_out[i] = e;
+        }
+        if (io.d_outcome_out && gl == 0u) {
+            Pos p = pos_from_loc(v, loc);
+            io.d_outcome_out[i] = commit_event<kLds>(v, p, t, cnt) ? NH_EVENT_SPECIATION : p.loc;
+        }
+        if (io.d_step_loc_out && io.d_step_t_out) {
+            // one group step (event, then the search from the new location, finished by the full
+            // group search when the first pass cannot decide)
+            Pos p = pos_from_loc(v, loc);
+            double tt = t;
+            uint2 row = table_row<kLds>(v, p);
+            const uint32_t st = group_step<kLds>(v, p, tt, row, gl, grp_base, cnt);
+            if (st == kStepSlow) tt = next_event_time_group(v, p.loc, tt, gl, grp_base, err, cnt);
+            if (gl == 0u) {
+                io.d_step_loc_out[i] = st == kStepSpeciated ? NH_EVENT_SPECIATION : p.loc;
+                io.d_step_t_out[i] = st == kStepSpeciated ? t : tt;
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Event stream (sections "Sorting Events using the Water-Level Algorithm" and
 // "Reporting Coalescence Events Independently").  After a completed run each
@@ -3614,5 +3680,40 @@ NH_API int nh_measure_event_latency(const nh_scenario *scenario, uint64_t seed, 
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, a, b));
     *ns_per_event = (double)ms * 1e6 / steps;
+    return NH_OK;
+}
+
+NH_API int nh_eval_primitives(const nh_scenario *scenario, uint64_t seed, uint64_t n, const nh_primitive_io *io,
+                              uint32_t use_lds, void *stream_ptr) {
+    if (!scenario || !io) return fail(NH_EINVAL, "NULL scenario or io");
+    if ((!io->d_ctr) != (!io->d_philox_out) || (!io->d_r) != (!io->d_log_out) || (!io->d_loc) != (!io->d_t) ||
+        (!io->d_step_loc_out) != (!io->d_step_t_out))
+        return fail(NH_EINVAL, "primitive inputs and outputs come in pairs");
+    if (!io->d_loc && (io->d_next_out || io->d_next_group_out || io->d_outcome_out || io->d_step_loc_out))
+        return fail(NH_EINVAL, "event outputs need d_loc and d_t");
+    if (n == 0) return NH_OK;
+    hipStream_t stream = (hipStream_t)stream_ptr;
+    nh_job job{};
+    job.scenario = scenario;
+    job.seed = seed;
+    JobDev hd;
+    job_descriptor(hd, job, nullptr, nullptr, 0, 64, 0);
+    const bool lds = use_lds && scenario->mode == NH_DISPERSAL_SHARED && scenario->n_shared <= kLdsTableMax;
+    const size_t lds_bytes = lds ? sizeof(uint4) * scenario->n_shared : 0;
+    AsyncScratch S{stream, nullptr, {}};
+    JobDev *d_job = nullptr;
+    uint32_t *err = nullptr;
+    if (int rc = S.take(d_job, 1)) return rc;
+    if (int rc = S.take(err, 1)) return rc;
+    HIP_TRY(hipMemcpyAsync(d_job, &hd, sizeof hd, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemsetAsync(err, 0, sizeof(uint32_t), stream));
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((n * kGroup + 255) / 256, 1u << 16);
+    if (lds) k_primitives<true><<<blocks, 256, lds_bytes, stream>>>(d_job, n, *io, err);
+    else k_primitives<false><<<blocks, 256, 0, stream>>>(d_job, n, *io, err);
+    HIP_TRY(hipGetLastError());
+    uint32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, err, sizeof herr, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (herr) return fail(NH_EDEVICE, "an event-time search ran away (flags %#x)", herr);
     return NH_OK;
 }
