@@ -2,8 +2,9 @@
 must equal the CPU oracle's bit for bit, on the same seeded inputs.
 
 Small and ragged cases are compared in full; the full-size workloads are
-compared in full where the culled oracle is fast (configs 1 and 2) and on
-uniformly sampled outputs traced one by one otherwise (configs 3 and 4),
+compared in full where the culled oracle is fast (configs 1 and 2, and the
+256-scenario mix, whose oracle runs in a pool of host processes while the GPU
+works) and on uniformly sampled outputs traced one by one otherwise (config 3),
 together with properties that hold at any size (richness = distinct ids,
 duplicates agree, results independent of batching and tuning)."""
 import os
@@ -252,41 +253,61 @@ def test_config3_full_size_sampled(B):
 # Config 4: 256 scenarios in one batch                                         #
 # --------------------------------------------------------------------------- #
 
-def test_config4_batch_sampled_and_alone_equals_mix(B, torch_mod):
+def test_config4_full_parity_and_alone_equals_mix(B, torch_mod):
+    """All 256 scenarios of the mix (38.6 M samples) in one batch: every species id equals the
+    culled oracle's (run meanwhile in a separate process pool on the host's cores, compared by a
+    digest of each scenario's species array), and a few scenarios run alone equal the mix."""
+    import hashlib
+    import json
+    import subprocess
     torch = torch_mod
-    wls = W.config4()
-    dev = torch.device("cuda:0")
-    say("config 4: creating 256 scenarios")
-    scns = [B.Scenario.from_workload(w) for w in wls]
-    samples = [torch.from_numpy(w.samples.astype(np.int64)).to(dev) for w in wls]
-    outs = [torch.empty(len(w.samples), dtype=torch.int64, device=dev) for w in wls]
-    rich = torch.zeros(len(wls), dtype=torch.int64, device=dev)
-    jobs = [(scns[k], wls[k].seeds[0], samples[k], outs[k], rich[k:k + 1]) for k in range(len(wls))]
-    n_total = sum(len(w.samples) for w in wls)
-    ws = torch.empty(B.workspace_bytes(n_total, len(jobs)), dtype=torch.uint8, device=dev)
-    say("config 4: batch run of", n_total, "lineages")
-    t0 = time.time()
-    stats = B.batch_run(jobs, ws)
-    torch.cuda.synchronize()
-    say(f"config 4: {time.time() - t0:.2f} s, events {sum(s['events'] for s in stats)}")
-    got_rich = rich.cpu().numpy()
-    rng = np.random.default_rng(4)
-    budget_events = 0
-    for k, w in enumerate(wls):
-        got = outs[k].cpu().numpy().view(np.uint64)
-        assert got_rich[k] == len(np.unique(got)) == stats[k]["richness"]
-        osc = oracle.Scenario(w.capacity, w.weights, w.nu)
-        m = 2 if w.nu >= 1e-4 else 1
-        pick = rng.choice(len(w.samples), size=m, replace=False)
-        ref, _, ev = osc.simulate_naive(w.seeds[0], w.samples[pick])
-        budget_events += int(ev.sum())
-        assert np.array_equal(got[pick], ref), (k, w.name)
-    say("config 4: oracle traced events", budget_events)
+    here = os.path.dirname(os.path.abspath(__file__))
+    pool = subprocess.Popen([sys.executable, os.path.join(here, "oracle_pool.py"), "--workers", "16"],
+                            stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+    try:
+        wls = W.config4()
+        dev = torch.device("cuda:0")
+        say("config 4: creating 256 scenarios")
+        scns = [B.Scenario.from_workload(w) for w in wls]
+        samples = [torch.from_numpy(w.samples.astype(np.int64)).to(dev) for w in wls]
+        outs = [torch.empty(len(w.samples), dtype=torch.int64, device=dev) for w in wls]
+        rich = torch.zeros(len(wls), dtype=torch.int64, device=dev)
+        jobs = [(scns[k], wls[k].seeds[0], samples[k], outs[k], rich[k:k + 1]) for k in range(len(wls))]
+        n_total = sum(len(w.samples) for w in wls)
+        ws = torch.empty(B.workspace_bytes(n_total, len(jobs)), dtype=torch.uint8, device=dev)
+        say("config 4: batch run of", n_total, "lineages")
+        t0 = time.time()
+        stats = B.batch_run(jobs, ws)
+        torch.cuda.synchronize()
+        say(f"config 4: {time.time() - t0:.2f} s, events {sum(s['events'] for s in stats)}")
+        got_rich = rich.cpu().numpy()
+        got = [outs[k].cpu().numpy().view(np.uint64) for k in range(len(wls))]
+        for k in range(len(wls)):
+            assert got_rich[k] == len(np.unique(got[k])) == stats[k]["richness"]
+        say("config 4: waiting for the oracle pool")
+        out, err = pool.communicate(timeout=600)
+    finally:
+        if pool.poll() is None:
+            pool.kill()
+            pool.wait()
+    assert pool.returncode == 0, err[-2000:]
+    ref = {d["k"]: d for d in (json.loads(line) for line in out.splitlines() if line.startswith("{"))}
+    assert sorted(ref) == list(range(len(wls)))
+    bad = [k for k in range(len(wls))
+           if hashlib.sha256(got[k].astype("<u8").tobytes()).hexdigest() != ref[k]["sha256"]
+           or got_rich[k] != ref[k]["richness"]]
+    if bad:  # name the first differing samples of the first bad scenario
+        k = bad[0]
+        osc = oracle.Scenario(wls[k].capacity, wls[k].weights, wls[k].nu, mode=wls[k].mode)
+        exp, _, _ = osc.simulate_culled(wls[k].seeds[0], wls[k].samples, 2.0)
+        diff = np.flatnonzero(exp != got[k])[:5]
+        raise AssertionError(f"{len(bad)} scenarios differ; scenario {k} ({wls[k].name}) at samples {diff.tolist()}")
+    say("config 4: all", len(wls), "scenarios equal the oracle")
     # batch-alone == batch-mix for a few scenarios of different sizes
     for k in (0, 1, 2, int(np.argmin([w.individuals for w in wls]))):
         say("config 4 alone:", wls[k].name)
         alone, r, _ = B.simulate(scns[k], wls[k].seeds[0], wls[k].samples)
-        assert np.array_equal(alone, outs[k].cpu().numpy().view(np.uint64))
+        assert np.array_equal(alone, got[k])
         assert r == got_rich[k]
 
 
