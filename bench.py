@@ -116,7 +116,9 @@ def latency_bound(B, scn, samples, out, ws, cfg, stream, run_ms: float) -> dict:
     ns = B.measure_event_latency(scn, 42, 20000, stream)
     bound_ms = path * ns * 1e-6
     return {"path_events": path, "event_ns": ns, "bound_ms": bound_ms, "run_ms": run_ms, "frac": bound_ms / run_ms,
-            "what": "longest sample path in events x lone-lineage per-event latency, vs the seed-42 run"}
+            "what": "longest sample path in events x lone-lineage per-event latency, vs the seed-42 run",
+            # each event of the run once (no copies of coalesced lineages): independent of the knobs
+            "distinct_events": res["n_events"], "distinct_events_per_s": res["n_events"] / (run_ms * 1e-3)}
 
 
 def cpu_baseline(wl, budget_s: float) -> dict:
