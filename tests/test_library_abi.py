@@ -128,3 +128,19 @@ def test_event_stream_rejects_bad_calls_before_touching_the_gpu(B):
 def test_implicit_scenario_validation(B, J, Jm, m, nu):
     h = C.c_void_p()
     assert B.nh_scenario_create_implicit(J, Jm, m, nu, None, C.byref(h)) == B.NH_EINVAL
+
+
+def test_measurement_and_primitive_entry_points_reject_bad_calls_before_touching_the_gpu(B):
+    from paper_2108_05815_amd import binding as bd
+    x = C.c_double()
+    assert B.nh_measure_event_latency(None, 1, 100, C.byref(x), None) == B.NH_EINVAL
+    stand_in = C.create_string_buffer(64)  # a non-NULL scenario handle these checks never read
+    assert B.nh_measure_event_latency(C.addressof(stand_in), 1, 0, C.byref(x), None) == B.NH_EINVAL
+    assert B.nh_eval_primitives(None, 1, 1, None, 0, None) == B.NH_EINVAL
+    io = bd.nh_primitive_io()
+    io.d_ctr = 256  # an input without its output
+    assert B.nh_eval_primitives(C.addressof(stand_in), 1, 1, C.byref(io), 0, None) == B.NH_EINVAL
+    io = bd.nh_primitive_io()
+    io.d_next_out = 256  # an event output without locations and times
+    assert B.nh_eval_primitives(C.addressof(stand_in), 1, 1, C.byref(io), 0, None) == B.NH_EINVAL
+    assert "d_loc" in bd.nh_last_error().decode()
