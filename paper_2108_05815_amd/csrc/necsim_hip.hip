@@ -80,6 +80,7 @@ constexpr uint32_t kJobBadSample = 2u;       // JobState.flags: a sample id was 
 constexpr uint32_t kErrRunaway = 2u;
 constexpr uint32_t kErrHashFull = 4u;
 constexpr uint32_t kMaxHorizons = 1024;
+constexpr double kLongRoundS = 40e-6;  // mean round time from which the host enqueues the tail round by round
 constexpr uint32_t kLdsTableMax = 4096; // shared-table entries staged in LDS (64 KiB)
 
 // ---------------------------------------------------------------------------
@@ -2759,7 +2760,9 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
     // Optional HIP-event bracketing of every round launch (graph or kernel).
     thread_local std::vector<hipEvent_t> ev_pool;
     uint32_t ev_used = 0;
-    auto enqueue = [&]() -> int {
+    // whole: a graph of cfg.rounds_per_graph rounds (when graphs are in use), else one round
+    auto enqueue = [&](bool whole) -> int {
+        const bool as_graph = use_graph && whole;
         if (cfg.event_timing) {
             while (ev_pool.size() < 2ull * (ev_used + 1)) {
                 hipEvent_t e;
@@ -2768,14 +2771,14 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
             }
             HIP_TRY(hipEventRecord(ev_pool[2 * ev_used], stream));
         }
-        if (use_graph) HIP_TRY(hipGraphLaunch(exec, stream));
+        if (as_graph) HIP_TRY(hipGraphLaunch(exec, stream));
         else launch_round(stream);
         HIP_TRY(hipGetLastError());
         if (cfg.event_timing) {
             HIP_TRY(hipEventRecord(ev_pool[2 * ev_used + 1], stream));
             ++ev_used;
         }
-        rounds_enqueued += per_launch;
+        rounds_enqueued += as_graph ? per_launch : 1u;
         return NH_OK;
     };
     const auto t_start = clock::now();
@@ -2783,9 +2786,15 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
     bool suspended = false;
     if (n_total) {
         // Keep two launches in flight; stop when a round reports an empty queue, or, past
-        // cfg.max_rounds, once every enqueued round has run.
-        if (int rc = enqueue()) return rc;
-        if (int rc = enqueue()) return rc;
+        // cfg.max_rounds, once every enqueued round has run.  Whatever is enqueued past the
+        // last round still runs (two near-empty launches per round, about 9 us), which is
+        // felt in a short single-job run.  There the host keeps one graph and two rounds
+        // ahead of the device (not two graphs), and once the queue is shorter than the
+        // 8-lanes-per-lineage threshold and rounds have been long enough for launch overhead
+        // not to matter, it enqueues single rounds, two ahead, instead of whole graphs.  A
+        // multi-job batch runs hundreds of rounds and keeps two whole graphs ahead.
+        if (int rc = enqueue(true)) return rc;
+        if (int rc = enqueue(true)) return rc;
         uint64_t spins = 0;
         for (;;) {
             const unsigned long long word = __atomic_load_n(st.host, __ATOMIC_ACQUIRE);
@@ -2803,8 +2812,14 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
                 suspended = true;
                 break;
             }
-            if (!capped && rounds_enqueued < completed + 2 * per_launch) {
-                if (int rc = enqueue()) return rc;
+            bool whole = true;
+            if (use_graph && single && completed > 0 && live < ra.coop_max) {
+                const double el = std::chrono::duration<double>(clock::now() - t_start).count();
+                whole = el < kLongRoundS * (double)completed;
+            }
+            const uint64_t ahead = !whole ? 2ull : single ? per_launch + 2ull : 2ull * per_launch;
+            if (!capped && rounds_enqueued < completed + ahead) {
+                if (int rc = enqueue(whole)) return rc;
                 continue;
             }
             if ((++spins & 255) == 0) {
