@@ -105,18 +105,68 @@ def chain_events(ev, co) -> int:
     return best
 
 
+def horizon_table(cfg, t_max: float) -> list:
+    """The horizons of a single-job run, as the library builds them from the config (same defaults
+    for unset fields): h[0] = 0, h[1] = horizon0, then steps of min(step_max, h (growth - 1));
+    past the library's 1024 entries its last step repeats."""
+    h0 = cfg.horizon0 if cfg.horizon0 > 0 else 0.5
+    g = cfg.horizon_growth if cfg.horizon_growth > 1.0 else 1.25
+    smax = cfg.horizon_step_max if cfg.horizon_step_max > 0 else 4096.0
+    h = [0.0, h0]
+    while h[-1] < t_max:
+        step = min(smax, h[-1] * (g - 1.0)) if len(h) < 1024 else h[1023] - h[1022]
+        h.append(h[-1] + step)
+    return h
+
+
+def window_maxima(ev, co, horizons) -> list:
+    """Per horizon window (h[k], h[k+1]]: the most events one lineage entering the window commits
+    inside it; the round of that window cannot end sooner.  A lineage's path is followed through
+    the stream: after an arrival comes the event at that location whose prior event time is the
+    arrival's time, or, for an arrival that coalesced there, the event of the lineage it joined.
+    A window's entries are the events whose earliest prior event time lies before it."""
+    t = ev["t"]
+    tl, pl, ol, xl = t.tolist(), ev["t_prior"].tolist(), ev["origin"].tolist(), ev["outcome"].tolist()
+    first = {(pl[i], ol[i]): i for i in range(len(tl))}
+    joined = {(tc, loc): tp for tc, tp, loc in zip(co["t"].tolist(), co["t_parent"].tolist(), co["loc"].tolist())}
+    h = np.asarray(horizons, dtype=np.float64)
+    k = (np.searchsorted(h, t, side="left") - 1).tolist()
+    cnt = [0] * len(tl)
+    for i in range(len(tl) - 1, -1, -1):  # successors come later in time order
+        c = 1
+        if xl[i] != 0xFFFFFFFF:
+            key = (tl[i], xl[i])
+            j = first.get(key)
+            if j is None:
+                j = first[(joined[key], xl[i])]
+            if k[j] == k[i]:
+                c += cnt[j]
+        cnt[i] = c
+    m = [0] * ((max(k) + 1) if k else 0)
+    for i in range(len(tl)):
+        if pl[i] <= h[k[i]] and cnt[i] > m[k[i]]:
+            m[k[i]] = cnt[i]
+    return m
+
+
 def latency_bound(B, scn, samples, out, ws, cfg, stream, run_ms: float) -> dict:
     """The serial bound of the seed-42 simulate: the events on its longest sample path, each waiting
     on the previous one, times the per-event latency of a lone lineage (measured with the round
     kernel's group step); frac = bound / the run's stream time."""
     jobs = [(scn, 42, samples, out, None)]
-    B.batch_run(jobs, ws, cfg, stream)
+    run_rounds = B.batch_run(jobs, ws, cfg, stream)[0]["rounds"]
     res = B.event_stream(jobs, ws, stream=stream)[0]
     path = chain_events(res["events"], res["coalescences"])
+    ev = res["events"]
+    windows = window_maxima(ev, res["coalescences"], horizon_table(cfg, float(ev["t"].max()) if len(ev) else 0.0))
     ns = B.measure_event_latency(scn, 42, 20000, stream)
     bound_ms = path * ns * 1e-6
+    sched_ms = sum(windows) * ns * 1e-6
     return {"path_events": path, "event_ns": ns, "bound_ms": bound_ms, "run_ms": run_ms, "frac": bound_ms / run_ms,
             "what": "longest sample path in events x lone-lineage per-event latency, vs the seed-42 run",
+            # the horizon rounds' own bound: each round waits for the busiest lineage of its window
+            "schedule": {"rounds": len(windows), "run_rounds": run_rounds, "events": sum(windows), "bound_ms": sched_ms,
+                         "frac": sched_ms / run_ms, "per_round_events": windows},
             # each event of the run once (no copies of coalesced lineages): independent of the knobs
             "distinct_events": res["n_events"], "distinct_events_per_s": res["n_events"] / (run_ms * 1e-3)}
 

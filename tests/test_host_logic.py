@@ -109,3 +109,41 @@ def test_chain_events_is_the_longest_sample_path(case):
     c["t"], c["t_parent"], c["loc"] = co["t"], co["parent"], co["loc"]
     _, _, events = sc.simulate_naive(seed, s)
     assert bench.chain_events(e, c) == int(events.max())
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_window_maxima_are_the_busiest_sample_path_of_each_window(case):
+    """bench.py's per-window maxima, read from an event stream, equal the most events that any
+    sample's own path (the oracle tracing it alone) has inside each horizon window, for several
+    horizon schedules."""
+    import types
+
+    import numpy as np
+    import bench
+    import oracle
+    from paper_2108_05815_amd import workloads as W
+    cap, w, nu, seed = [(np.ones((16, 16), np.uint32), W.gaussian_kernel(1.5, 3), 0.02, 3),
+                        (np.full((10, 10), 2, np.uint32), np.ones((3, 3)), 0.01, 5),
+                        (np.array([[50]], np.uint32), np.ones((1, 1)), 0.01, 7)][case]
+    sc = oracle.Scenario(cap, w, nu)
+    s = np.arange(sc.individuals, dtype=np.uint64)
+    ev, co = sc.event_stream(seed, s)
+    e = np.zeros(len(ev["t"]), dtype=[("t", "<f8"), ("t_prior", "<f8"), ("origin", "<u4"), ("outcome", "<u4")])
+    e["t"], e["t_prior"], e["origin"], e["outcome"] = ev["t"], ev["prior"], ev["origin"], ev["outcome"]
+    c = np.zeros(len(co["t"]), dtype=[("t", "<f8"), ("t_parent", "<f8"), ("loc", "<u4"), ("reserved", "<u4")])
+    c["t"], c["t_parent"], c["loc"] = co["t"], co["parent"], co["loc"]
+    traces = []
+    for x in s:
+        times, _, _, _, done = sc.trace(seed, int(x))
+        assert done
+        traces.append(times)
+    for h0, g, smax in [(0.5, 1.25, 4096.0), (2.0, 2.0, 8.0), (1.0, 3.0, 4096.0)]:
+        h = bench.horizon_table(types.SimpleNamespace(horizon0=h0, horizon_growth=g, horizon_step_max=smax),
+                                float(e["t"].max()))
+        assert h[:2] == [0.0, h0] and all(b - a <= smax + 1e-12 for a, b in zip(h, h[1:]))
+        got = bench.window_maxima(e, c, h)
+        want = np.zeros(len(got), np.int64)
+        for times in traces:
+            k = np.searchsorted(np.asarray(h), times, side="left") - 1
+            want = np.maximum(want, np.bincount(k, minlength=len(got)))
+        assert got == want.tolist() and sum(got) >= bench.chain_events(e, c)
