@@ -119,7 +119,9 @@ typedef struct {
     double horizon_step_max; /* cap on one round's horizon advance, default 4096 */
     uint32_t block_size;  /* threads per workgroup of the round kernel (64..1024), default 256 */
     uint32_t blocks_per_cu; /* workgroups per compute unit, default 4 */
-    uint32_t rounds_per_graph; /* round kernels per captured graph (1 = plain launches), default 8 */
+    uint32_t rounds_per_graph; /* round kernels per captured graph (1 = plain launches), default 8; a
+                                  single-job run launches its tail (queue below coop_max, rounds of
+                                  40 us or more on average) one round at a time */
     uint32_t event_timing; /* 1: bracket every round launch with HIP events (fills round_kernel_ms) */
     uint32_t coop_max;    /* queues shorter than this many lineages run 8 lanes per lineage; default
                              (0): a launch's lane count / 16 + 1; 1 keeps one lane per lineage always */
