@@ -214,3 +214,24 @@ def test_event_stream_of_the_256_torus(B, torch_mod):
         t, parent, loc = float(co["t"][i]), float(co["t_parent"][i]), int(co["loc"][i])
         assert 0.0 <= parent < t and (t, loc) in arrivals
         assert parent == 0.0 or (parent, loc) in arrivals
+
+
+@pytest.mark.parametrize("knobs", [dict(), dict(horizon0=2.0, horizon_growth=2.0),
+                                   dict(horizon0=0.25, horizon_growth=1.5, horizon_step_max=16.0)],
+                         ids=["default", "2x2", "capped"])
+def test_one_round_per_horizon_window(B, torch_mod, knobs):
+    """A single-job run takes one round per horizon window up to the window of its last event,
+    with the horizons bench.py derives from the config, so the per-window maxima it reports
+    describe the run's own rounds."""
+    import bench
+    name, kw, samples, seed = CASES[2]
+    osc, scn = _scenarios(B, kw)
+    samples = _samples(osc, samples)
+    cfg = B.make_config(**knobs)
+    jobs, ws, _, st = _run(B, torch_mod, [(scn, seed, samples)], cfg)
+    got = B.event_stream(jobs, ws)[0]
+    ev, co = got["events"], got["coalescences"]
+    m = bench.window_maxima(ev, co, bench.horizon_table(cfg, float(ev["t"].max())))
+    say(name, knobs, "rounds", st[0]["rounds"], "windows", len(m))
+    assert len(m) == st[0]["rounds"]
+    assert m[-1] > 0 and sum(m) >= bench.chain_events(ev, co)
