@@ -195,7 +195,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method shards by samples with no "
-              "communication, and multi-GPU runs are not part of this build.", file=sys.stderr)
+              "communication, and this benchmark measures a single GPU.", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.copy_calibration:
