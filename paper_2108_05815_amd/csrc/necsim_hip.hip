@@ -1218,12 +1218,19 @@ __device__ __forceinline__ void round_one_lane(const RoundArgs &A, uint32_t r, u
         w_single = horizon_of(A.htab, r - A.jobs[0].start_round);
     }
     WaveQueues q;
+    uint32_t iter = 0; // wave-uniform
     bool has = false;
     uint32_t g = 0, jb = 0, ev = 0;
     Pos p = {0, 0, 0, 0};
     double t = 0.0, horizon = w_single;
 
     while (true) {
+        // A wave whose lanes are all busy does not reserve, so it would not learn that other waves
+        // have reserved the rest of the queue: every 8th iteration it reads the shared cursor (one
+        // relaxed load, consumed after the event step, so its latency hides behind it).
+        const bool peek = q.open && q.chunk_pos >= q.chunk_end && (++iter & 7u) == 0u;
+        uint32_t reserved = 0;
+        if (peek) reserved = __hip_atomic_load(cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t need = __ballot(!has);
         bool retire = false;
         if (need && (q.open || q.chunk_pos < q.chunk_end)) {
@@ -1276,6 +1283,7 @@ __device__ __forceinline__ void round_one_lane(const RoundArgs &A, uint32_t r, u
                 } while (drained && !(finish_dead | finish_live));
             }
         }
+        if (peek && __builtin_amdgcn_readfirstlane(reserved) >= n_in) q.open = false; // the cursor only grows
         if (finish_dead) {
             lin.species[g] = speciated ? species_of(v, p.loc, t) : 0ull;
             lin.spec_loc[g] = p.loc;
@@ -1324,12 +1332,18 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
         w_single = horizon_of(A.htab, r - A.jobs[0].start_round);
     }
     WaveQueues q;
+    uint32_t iter = 0; // wave-uniform
     bool has = false;
     uint32_t g = 0, jb = 0, ev = 0;
     Pos p = {0, 0, 0, 0};
     double t = 0.0, horizon = w_single;
 
     while (true) {
+        // as in the one-lane layout: a wave whose groups are all busy learns from the shared cursor
+        // (every 8th iteration) that the queue is fully reserved
+        const bool peek = q.open && q.chunk_pos >= q.chunk_end && (++iter & 7u) == 0u;
+        uint32_t reserved = 0;
+        if (peek) reserved = __hip_atomic_load(cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t need = __ballot(leader && !has);
         bool retire = false;     // set on the leader lane of a group whose candidate was merged
         uint32_t retire_jb = 0;
@@ -1401,6 +1415,7 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
                 }
             }
         }
+        if (peek && __builtin_amdgcn_readfirstlane(reserved) >= n_in) q.open = false; // the cursor only grows
         if (finish_dead) {
             if (leader) {
                 const uint32_t sloc = speciated ? at : p.loc;
