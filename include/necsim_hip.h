@@ -117,12 +117,14 @@ typedef struct {
     double horizon0;      /* first cull horizon (time units), default 0.5 */
     double horizon_growth;/* horizon multiplier per round (> 1), default 1.25 */
     double horizon_step_max; /* cap on one round's horizon advance, default 4096 */
-    uint32_t block_size;  /* threads per workgroup of the round kernel (64..1024), default 256 */
-    uint32_t blocks_per_cu; /* workgroups per compute unit, default 4 */
-    uint32_t rounds_per_graph; /* round kernels per captured graph (1 = plain launches), default 8; a
-                                  single-job run launches its tail (queue below coop_max, rounds of
-                                  40 us or more on average) one round at a time */
-    uint32_t event_timing; /* 1: bracket every round launch with HIP events (fills round_kernel_ms) */
+    uint32_t block_size;  /* threads per workgroup of the round kernel: a multiple of 64 up to 256,
+                             default 256 */
+    uint32_t blocks_per_cu; /* workgroups per compute unit, default 4; a persistent run takes at most as
+                               many as stay resident together (the kernel's occupancy) */
+    uint32_t rounds_per_graph; /* NH_LAUNCH_GRAPHS only: round kernels per captured graph (1 = plain
+                                  launches), default 8; a single-job run launches its tail (queue below
+                                  coop_max, rounds of 40 us or more on average) one round at a time */
+    uint32_t event_timing; /* 1: bracket the round kernels with HIP events (fills round_kernel_ms) */
     uint32_t coop_max;    /* queues shorter than this many lineages run 8 lanes per lineage; default
                              (0): a launch's lane count / 16 + 1; 1 keeps one lane per lineage always */
     uint32_t table_placement; /* 0: stage a shared dispersal table in LDS for single-job runs when it
@@ -133,13 +135,20 @@ typedef struct {
                              wave priority, on blocks of their own, and advances its horizon by
                              solo_step per round (its serial tail no longer waits on the horizon
                              schedule of young jobs); default 0: off */
-    uint32_t reserved;    /* set to zero */
+    uint32_t launch;      /* NH_LAUNCH_PERSISTENT (0, default): one launch runs every round of the run
+                             (a grid barrier between rounds); NH_LAUNCH_GRAPHS: one launch per round,
+                             replayed from captured graphs while the host polls the round count */
     double solo_step;     /* horizon advance per round of such a job, default 512 */
     uint32_t max_rounds;  /* nh_batch_run / nh_batch_resume: stop after at least this many rounds of the
                              call (at the first launch boundary past it) and return NH_SUSPENDED with
                              the run's whole state in the workspace; default 0: run to the end */
-    uint32_t reserved2;   /* set to zero */
+    uint32_t barrier_wait_ms; /* persistent launches: the longest a workgroup waits at one grid barrier
+                                 before it stops the run (NH_EDEVICE; the kernel exits either way);
+                                 default 0: min(timeout_s, 60 s) */
 } nh_config;
+
+#define NH_LAUNCH_PERSISTENT 0u
+#define NH_LAUNCH_GRAPHS 1u
 
 /* Per-job counters of one run. */
 typedef struct {
@@ -153,7 +162,7 @@ typedef struct {
     /* Totals of the whole run (the same for every job of a batch): */
     uint64_t philox_calls;   /* Philox4x32-10 blocks evaluated */
     uint64_t exp_draws;      /* exponential waiting-time draws (logarithms) */
-    uint64_t round_kernels;  /* round-kernel launches */
+    uint64_t round_kernels;  /* round-kernel launches (1 for a persistent run) */
     double round_kernel_ms;  /* HIP-event time of all round launches (cfg.event_timing), else 0 */
 } nh_stats;
 
@@ -317,6 +326,28 @@ int nh_event_stream(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint
 int nh_simulate_device(const nh_scenario *scenario, uint64_t seed, const uint64_t *d_sample_ids, uint64_t n,
                        uint64_t *d_species_out, uint64_t *d_richness_out, const nh_config *cfg, nh_stats *stats,
                        void *stream);
+
+/* One job with device buffers, enqueue-only: every step of the run (set-up from
+ * kernel arguments, lineage init, one persistent launch that runs all horizon
+ * rounds on the device with a grid barrier between them, output) is enqueued
+ * on `stream` and the call returns without waiting for the device (paper,
+ * section "The Independent Algorithm on the GPU": the host<->device crossing
+ * between steps is what the GPU path paid for).  The caller synchronises
+ * `stream` (or records an event) before reading d_species_out (n u64) and
+ * *d_richness_out (one u64, may be NULL).  The workspace is taken
+ * stream-ordered from a library-owned pool of the current device and given
+ * back stream-ordered; the persistent launch itself runs on a library stream
+ * per device joined to `stream` by events, so persistent runs of one device
+ * never overlap.  cfg may be NULL; cfg->launch must be NH_LAUNCH_PERSISTENT and
+ * cfg->max_rounds 0.
+ * Errors found before enqueueing are returned (NH_EINVAL: NULL buffers with
+ * n > 0, n >= 2^31, a bad cfg; NH_EDEVICE: a HIP error).  Errors found on the
+ * device cannot be returned: a sample id >= N, or a run that stops early (its
+ * time limit cfg->timeout_s, a kernel error flag, a barrier wait beyond
+ * cfg->barrier_wait_ms), set *d_richness_out to ~0 (UINT64_MAX) and leave
+ * d_species_out unspecified. */
+int nh_simulate_async(const nh_scenario *scenario, uint64_t seed, const uint64_t *d_sample_ids, uint64_t n,
+                      uint64_t *d_species_out, uint64_t *d_richness_out, const nh_config *cfg, void *stream);
 
 /* One job with host buffers: uploads the samples, runs, downloads species
  * (n u64) and the richness.  Blocking; uses the default stream. */

@@ -45,8 +45,8 @@ class nh_config(C.Structure):
     _fields_ = [("horizon0", C.c_double), ("horizon_growth", C.c_double), ("horizon_step_max", C.c_double),
                 ("block_size", C.c_uint32), ("blocks_per_cu", C.c_uint32), ("rounds_per_graph", C.c_uint32),
                 ("event_timing", C.c_uint32), ("coop_max", C.c_uint32), ("table_placement", C.c_uint32),
-                ("timeout_s", C.c_double), ("solo_max", C.c_uint32), ("reserved", C.c_uint32),
-                ("solo_step", C.c_double), ("max_rounds", C.c_uint32), ("reserved2", C.c_uint32)]
+                ("timeout_s", C.c_double), ("solo_max", C.c_uint32), ("launch", C.c_uint32),
+                ("solo_step", C.c_double), ("max_rounds", C.c_uint32), ("barrier_wait_ms", C.c_uint32)]
 
 
 class nh_stats(C.Structure):
@@ -75,6 +75,7 @@ class nh_stream_out(C.Structure):
 EVENT_DTYPE = np.dtype([("t", "<f8"), ("t_prior", "<f8"), ("origin", "<u4"), ("outcome", "<u4")])
 COALESCENCE_DTYPE = np.dtype([("t", "<f8"), ("t_parent", "<f8"), ("loc", "<u4"), ("reserved", "<u4")])
 NH_EVENT_SPECIATION = 0xFFFFFFFF
+NH_LAUNCH_PERSISTENT, NH_LAUNCH_GRAPHS = 0, 1
 
 
 class nh_primitive_io(C.Structure):
@@ -129,6 +130,9 @@ _lib.nh_eval_primitives.restype = C.c_int
 _lib.nh_simulate_device.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
                                     C.POINTER(nh_config), C.POINTER(nh_stats), C.c_void_p]
 _lib.nh_simulate_device.restype = C.c_int
+_lib.nh_simulate_async.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
+                                   C.POINTER(nh_config), C.c_void_p]
+_lib.nh_simulate_async.restype = C.c_int
 _lib.nh_simulate.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64), C.c_uint64, C.POINTER(C.c_uint64),
                              C.POINTER(C.c_uint64), C.POINTER(nh_stats)]
 _lib.nh_simulate.restype = C.c_int
@@ -168,6 +172,7 @@ nh_batch_resume = _lib.nh_batch_resume
 nh_event_stream = _lib.nh_event_stream
 nh_simulate_device = _lib.nh_simulate_device
 nh_simulate = _lib.nh_simulate
+nh_simulate_async = _lib.nh_simulate_async
 nh_last_error = _lib.nh_last_error
 nh_version = _lib.nh_version
 nh_measure_mix_peak = _lib.nh_measure_mix_peak
@@ -184,7 +189,7 @@ nh_server_destroy = _lib.nh_server_destroy
 
 EXPORTED = ["nh_scenario_create", "nh_scenario_create_implicit", "nh_scenario_destroy", "nh_scenario_individuals", "nh_scenario_table_bytes",
             "nh_workspace_bytes", "nh_scenario_footprint_bytes", "nh_batch_run", "nh_batch_resume", "nh_event_stream",
-            "nh_simulate_device",
+            "nh_simulate_device", "nh_simulate_async",
             "nh_simulate", "nh_last_error", "nh_version", "nh_server_bytes", "nh_server_create",
             "nh_server_submit", "nh_server_progress", "nh_server_poll", "nh_server_drain", "nh_server_destroy",
             "nh_measure_mix_peak", "nh_measure_gather", "nh_measure_event_latency", "nh_eval_primitives"]
@@ -288,6 +293,23 @@ def simulate(scenario: Scenario, seed: int, samples) -> tuple[np.ndarray, int, d
     _check(_lib.nh_simulate(scenario.handle, seed, s.ctypes.data_as(C.POINTER(C.c_uint64)), len(s),
                             out.ctypes.data_as(C.POINTER(C.c_uint64)), C.byref(rich), C.byref(st)), "nh_simulate")
     return out, int(rich.value), st.as_dict()
+
+
+def simulate_async(scenario: Scenario, seed: int, samples, out, rich=None, config: nh_config | None = None,
+                   stream=None) -> None:
+    """nh_simulate_async: enqueue one whole run on `stream` (torch.cuda.Stream or None for the current
+    one) and return at once.  samples: u64/int64 device tensor; out: int64 device tensor of the same
+    length; rich: one-element int64 device tensor or None (it reads -1, i.e. ~0, if the run failed
+    on the device).  Synchronise the stream before reading them."""
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    n = samples.numel()
+    _check(_lib.nh_simulate_async(scenario.handle, int(seed) & (2**64 - 1), samples.data_ptr() if n else None, n,
+                                  out.data_ptr() if out.numel() else None,
+                                  rich.data_ptr() if rich is not None else None,
+                                  C.byref(config) if config is not None else None, C.c_void_p(s.cuda_stream)),
+           "nh_simulate_async")
 
 
 def workspace_bytes(n_total: int, n_jobs: int) -> int:

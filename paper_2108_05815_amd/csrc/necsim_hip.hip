@@ -149,7 +149,20 @@ struct Ctl {
     uint32_t ring_pub;   // completions already copied to the host-mapped ring
     unsigned long long philox_calls; // Philox blocks evaluated (all domains)
     unsigned long long exp_draws;    // exponential waiting-time draws (logarithms)
+    // Persistent runs (k_run): grid barrier and stop state, reset before every launch.
+    uint32_t bar_arrived;            // workgroups arrived at the current barrier
+    uint32_t bar_gen;                // barriers completed
+    uint32_t stop;                   // kStop*: why the run ended (0: running)
+    uint32_t first_round;            // round the launch started with
+    unsigned long long t_start;      // device wall clock when the launch started
 };
+
+// Why a persistent run ended.
+constexpr uint32_t kStopDone = 1u;      // every lineage retired
+constexpr uint32_t kStopSuspended = 2u; // the round limit of the call was reached
+constexpr uint32_t kStopError = 3u;     // a kernel error flag, the run's time limit or a stalled barrier
+constexpr uint32_t kErrTimeout = 16u;   // the run exceeded its time limit
+constexpr uint32_t kErrStall = 32u;     // a barrier wait exceeded its limit (workgroups not all resident)
 
 // Lineage state.  loc/t are double-buffered by round parity: round r reads
 // [r & 1] and writes survivors to [(r + 1) & 1], so the state a cull insert
@@ -936,6 +949,11 @@ __global__ void k_setup(Ctl *ctl, JobState *js, const JobDev *jobs, uint32_t n_j
         ctl->exp_draws = 0;
         ctl->ring_head = 0;
         ctl->ring_pub = 0;
+        ctl->bar_arrived = 0;
+        ctl->bar_gen = 0;
+        ctl->stop = 0;
+        ctl->first_round = first_round;
+        ctl->t_start = 0;
     }
     for (uint32_t j = t; j < n_jobs; j += gridDim.x * blockDim.x) {
         js[j].remaining = jobs[j].n;
@@ -951,6 +969,40 @@ __global__ void k_setup(Ctl *ctl, JobState *js, const JobDev *jobs, uint32_t n_j
         js[j].abund_n = 0;
         js[j].sentinel_count = 0;
     }
+}
+
+// Set-up of a single-job run from kernel arguments alone (enqueue-only calls
+// copy nothing from the host): the job descriptor, the horizon table (the
+// same recurrence, in the same binary64 operations, as the host table of
+// nh_batch_run), the control block and the job's counters.
+__global__ void k_setup_single(Ctl *ctl, JobState *js, JobDev *jobs, JobDev job, double *htab, double h0,
+                               double growth, double step_max) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    jobs[0] = job;
+    htab[0] = 0.0;
+    htab[1] = h0;
+    for (uint32_t i = 2; i < kMaxHorizons; ++i) htab[i] = htab[i - 1] + fmin(step_max, htab[i - 1] * (growth - 1.0));
+    ctl->round = 1;
+    for (int k = 0; k < 3; ++k) {
+        ctl->count[k] = 0;
+        ctl->cursor[k] = 0;
+        ctl->solo[k] = 0;
+        ctl->solo_cursor[k] = 0;
+    }
+    ctl->blocks_done = 0;
+    ctl->error = 0;
+    ctl->n_jobs = 1;
+    ctl->philox_calls = 0;
+    ctl->exp_draws = 0;
+    ctl->ring_head = 0;
+    ctl->ring_pub = 0;
+    ctl->bar_arrived = 0;
+    ctl->bar_gen = 0;
+    ctl->stop = 0;
+    ctl->first_round = 1;
+    ctl->t_start = 0;
+    js[0] = JobState{};
+    js[0].remaining = job.n;
 }
 
 // Binary search: the job whose lineage range holds g (jobs sorted by lin_base).
@@ -1444,19 +1496,21 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
     wave_flush(q, obuf, &ctl->count[qout], act_out);
 }
 
-template <bool kSingleJob, bool kLds>
-__global__ __launch_bounds__(256) void k_round(RoundArgs A) {
-    const uint32_t r = A.ctl->round;
-    const uint32_t n_main = A.ctl->count[r % 3];
-    const uint32_t n_solo = kSingleJob ? 0u : A.ctl->solo[r % 3];
-    if (n_main == 0 && n_solo == 0) return;
-    __shared__ uint32_t out_stage[kWavesPerBlock][kOutBuf];
-    uint32_t *obuf = out_stage[threadIdx.x / 64];
+// Which part of a round a workgroup takes.  Multi-job runs: the first
+// workgroups take the solo queue, 8 lanes per lineage at raised wave priority
+// (the long serial tails of nearly finished jobs), at most a quarter of the
+// grid; the others take the main queue, as many as its length needs.  The
+// plan is workgroup-uniform.
+constexpr uint32_t kPlanIdle = 0, kPlanSolo = 1, kPlanLanes = 2, kPlanGroups = 3;
+struct RoundPlan {
+    uint32_t mode;  // kPlan*
+    uint32_t chunk; // queue items per reservation
+};
+
+template <bool kSingleJob>
+__device__ __forceinline__ RoundPlan plan_round(const RoundArgs &A, uint32_t n_main, uint32_t n_solo) {
+    RoundPlan pl{kPlanIdle, 0u};
     const uint32_t waves_per_block = blockDim.x / 64;
-    Counters cnt;
-    // Multi-job runs: the first blocks take the solo queue, 8 lanes per lineage at raised wave
-    // priority (these are the long serial tails of nearly finished jobs), at most a quarter of the
-    // grid; the other blocks take the main queue.
     uint32_t solo_blocks = 0;
     if constexpr (!kSingleJob) {
         if (n_solo) {
@@ -1464,41 +1518,213 @@ __global__ __launch_bounds__(256) void k_round(RoundArgs A) {
             solo_blocks = (uint32_t)min<uint64_t>(need, gridDim.x / 4); // the host keeps the grid >= 4
         }
         if (blockIdx.x < solo_blocks) {
-            __builtin_amdgcn_s_setprio(2);
             const uint64_t waves = (uint64_t)solo_blocks * waves_per_block;
-            const uint32_t chunk = (uint32_t)min<uint64_t>(32u, n_solo / (4 * waves));
-            round_group<false, false>(A, r, n_solo, cnt, obuf, chunk, true);
-            flush_counters_block(A.ctl, cnt);
-            return;
+            pl.mode = kPlanSolo;
+            pl.chunk = (uint32_t)min<uint64_t>(32u, n_solo / (4 * waves));
+            return pl;
         }
     }
-    if (n_main == 0) return;
+    if (n_main == 0) return pl;
     const uint32_t b = blockIdx.x - solo_blocks, grid = gridDim.x - solo_blocks;
     const bool group = n_main < A.coop_max;
     const uint64_t lanes_needed = (uint64_t)n_main * (group ? kGroup : 1u);
     const uint64_t blocks_needed = (lanes_needed + blockDim.x - 1) / blockDim.x;
-    if (b >= blocks_needed) return; // whole workgroup leaves together
-    if (kLds) { // stage the shared dispersal table (single job, shared mode, small table)
-        const uint32_t n_tab = A.jobs[0].n_shared;
-        const uint4 *__restrict__ src = A.jobs[0].table;
-        for (uint32_t i = threadIdx.x; i < n_tab; i += blockDim.x) nh_lds_table[i] = src[i];
-        __syncthreads();
-    }
+    if (b >= blocks_needed) return pl; // whole workgroup sits the round out
     // fair share of the queue per participating wave (a quarter of it per reservation), capped
     const uint64_t waves = min((uint64_t)grid, blocks_needed) * waves_per_block;
-    const uint32_t chunk = (uint32_t)min<uint64_t>(group ? 32u : 256u, n_main / (4 * waves));
-    if (group) round_group<kSingleJob, kLds>(A, r, n_main, cnt, obuf, chunk, false);
-    else round_one_lane<kSingleJob, kLds>(A, r, n_main, cnt, obuf, chunk, false);
+    pl.mode = group ? kPlanGroups : kPlanLanes;
+    pl.chunk = (uint32_t)min<uint64_t>(group ? 32u : 256u, n_main / (4 * waves));
+    return pl;
+}
+
+// Stages the shared dispersal table (single job, shared mode, small table) in LDS.
+__device__ __forceinline__ void stage_table(const RoundArgs &A) {
+    const uint32_t n_tab = A.jobs[0].n_shared;
+    const uint4 *__restrict__ src = A.jobs[0].table;
+    for (uint32_t i = threadIdx.x; i < n_tab; i += blockDim.x) nh_lds_table[i] = src[i];
+    __syncthreads();
+}
+
+// This workgroup's share of round r (plan pl), lane layout by the plan.
+template <bool kSingleJob, bool kLds>
+__device__ __forceinline__ void round_share(const RoundArgs &A, uint32_t r, const RoundPlan &pl, uint32_t n_main,
+                                            uint32_t n_solo, Counters &cnt, uint32_t *obuf) {
+    if constexpr (!kSingleJob) {
+        if (pl.mode == kPlanSolo) {
+            __builtin_amdgcn_s_setprio(2);
+            round_group<false, false>(A, r, n_solo, cnt, obuf, pl.chunk, true);
+            __builtin_amdgcn_s_setprio(0);
+            return;
+        }
+    }
+    if (pl.mode == kPlanGroups) round_group<kSingleJob, kLds>(A, r, n_main, cnt, obuf, pl.chunk, false);
+    else round_one_lane<kSingleJob, kLds>(A, r, n_main, cnt, obuf, pl.chunk, false);
+}
+
+template <bool kSingleJob, bool kLds>
+__global__ __launch_bounds__(256) void k_round(RoundArgs A) {
+    const uint32_t r = A.ctl->round;
+    const uint32_t n_main = A.ctl->count[r % 3];
+    const uint32_t n_solo = kSingleJob ? 0u : A.ctl->solo[r % 3];
+    const RoundPlan pl = plan_round<kSingleJob>(A, n_main, n_solo);
+    if (pl.mode == kPlanIdle) return;
+    __shared__ uint32_t out_stage[kWavesPerBlock][kOutBuf];
+    uint32_t *obuf = out_stage[threadIdx.x / 64];
+    Counters cnt;
+    if (kLds && pl.mode != kPlanSolo) stage_table(A);
+    round_share<kSingleJob, kLds>(A, r, pl, n_main, n_solo, cnt, obuf);
     flush_counters_block(A.ctl, cnt);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent run: one launch carries a run through all of its rounds.  The
+// workgroups (all resident: the grid is sized from the occupancy and launched
+// cooperatively) run a round, meet at a grid barrier whose last arrival runs
+// the round epilogue (advance the round, reset the next queues, decide whether
+// the run goes on), and start the next round.  Nothing returns to the host
+// between rounds, so the call that enqueues it can return at once.
+// ---------------------------------------------------------------------------
+struct RunArgs {
+    uint32_t max_rounds;          // rounds of this launch before it suspends (0: no limit)
+    uint32_t pad;
+    unsigned long long spin_ticks; // wall-clock ticks one barrier wait may take
+    unsigned long long run_ticks;  // wall-clock ticks the whole launch may take
+};
+
+struct RoundCtl {
+    uint32_t r, n_main, n_solo, stop;
+};
+
+// The round control words as the last epilogue left them (agent-scope loads).
+__device__ __forceinline__ RoundCtl read_round_ctl(Ctl *ctl, bool single) {
+    RoundCtl c;
+    c.r = __hip_atomic_load(&ctl->round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    c.n_main = __hip_atomic_load(&ctl->count[c.r % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    c.n_solo = single ? 0u : __hip_atomic_load(&ctl->solo[c.r % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    c.stop = __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return c;
+}
+
+// Device wall clock at the start of the launch (set by the first workgroup to start).
+__device__ __forceinline__ unsigned long long run_start(Ctl *ctl) {
+    return __hip_atomic_load(&ctl->t_start, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Round epilogue of a persistent run (one thread, after every workgroup has
+// finished round r): the same bookkeeping as k_advance, then the stop decision.
+__device__ __forceinline__ void run_epilogue(Ctl *ctl, const RunArgs &R) {
+    auto ld = [](uint32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+    auto st = [](uint32_t *p, uint32_t x) { __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+    const uint32_t r = ld(&ctl->round);
+    const uint32_t n_out = ld(&ctl->count[(r + 1) % 3]) + ld(&ctl->solo[(r + 1) % 3]);
+    st(&ctl->count[(r + 2) % 3], 0u);
+    st(&ctl->solo[(r + 2) % 3], 0u);
+    st(&ctl->solo_cursor[(r + 1) % 3], 0u);
+    st(&ctl->cursor[(r + 1) % 3], 0u);
+    st(&ctl->round, r + 1);
+    uint32_t stop = 0;
+    if (n_out == 0) {
+        stop = kStopDone;
+    } else if ((ld(&ctl->error) & ~kErrBadSample) != 0u) {
+        stop = kStopError; // a bad sample id only fails its own job
+    } else if (R.max_rounds != 0u && r + 1u - ld(&ctl->first_round) >= R.max_rounds) {
+        stop = kStopSuspended;
+    } else if (wall_clock64() - run_start(ctl) > R.run_ticks) {
+        atomicOr(&ctl->error, kErrTimeout);
+        stop = kStopError;
+    }
+    if (stop) atomicCAS(&ctl->stop, 0u, stop); // a workgroup that gave up waiting has stopped the run already
+}
+
+// Grid barrier between rounds.  Every workgroup calls it with the same gen
+// (barriers passed so far); the last to arrive runs the epilogue and releases
+// the others.  A wait is bounded: past R.spin_ticks, or once the run has been
+// stopped, a workgroup stops waiting, flags the run and leaves, and the round
+// loop then ends every workgroup.  On return the workgroup's copy of the
+// round control (sc) is current.
+__device__ __forceinline__ void grid_sync(Ctl *ctl, const RunArgs &R, uint32_t &gen, RoundCtl &sc, bool single) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence(); // release this workgroup's writes of the round (agent scope)
+        const uint32_t arrived = atomicAdd(&ctl->bar_arrived, 1u);
+        if (arrived == gridDim.x - 1u) {
+            __threadfence(); // acquire every workgroup's writes
+            __hip_atomic_store(&ctl->bar_arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            run_epilogue(ctl, R);
+            __hip_atomic_store(&ctl->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const unsigned long long t0 = wall_clock64();
+            // relaxed loads while waiting (an acquire per poll would invalidate the L2 each time)
+            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                if (__hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+                const unsigned long long now = wall_clock64();
+                // past the run's own time limit the run has timed out; otherwise a wait this long
+                // means workgroups that never arrive
+                const bool late = now - run_start(ctl) > R.run_ticks;
+                if (late || now - t0 > R.spin_ticks) {
+                    atomicOr(&ctl->error, late ? kErrTimeout : kErrStall);
+                    __hip_atomic_store(&ctl->stop, kStopError, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __threadfence(); // acquire the epilogue's writes and the other workgroups' round
+        sc = read_round_ctl(ctl, single);
+    }
+    ++gen;
+    __syncthreads();
+}
+
+template <bool kSingleJob, bool kLds>
+__global__ __launch_bounds__(256) void k_run(RoundArgs A, RunArgs R) {
+    __shared__ uint32_t out_stage[kWavesPerBlock][kOutBuf];
+    __shared__ RoundCtl sc;
+    uint32_t *obuf = out_stage[threadIdx.x / 64];
+    if (threadIdx.x == 0) {
+        // the first workgroup to start sets the launch's start time (k_run_reset cleared it)
+        atomicCAS(&A.ctl->t_start, 0ull, wall_clock64());
+        __threadfence();
+        sc = read_round_ctl(A.ctl, kSingleJob);
+    }
+    __syncthreads();
+    if (kLds) stage_table(A);
+    uint32_t gen = 0;
+    for (;;) {
+        const RoundCtl c = sc; // workgroup-uniform
+        if (c.stop != 0u) break;
+        const RoundPlan pl = plan_round<kSingleJob>(A, c.n_main, c.n_solo);
+        if (pl.mode != kPlanIdle) {
+            Counters cnt;
+            round_share<kSingleJob, kLds>(A, c.r, pl, c.n_main, c.n_solo, cnt, obuf);
+            flush_counters_block(A.ctl, cnt);
+        }
+        grid_sync(A.ctl, R, gen, sc, kSingleJob);
+    }
+}
+
+// Clears a persistent run's barrier and stop state before a launch (a resume
+// included: the run goes on from the round its control block holds).
+__global__ void k_run_reset(Ctl *ctl) {
+    ctl->bar_arrived = 0;
+    ctl->bar_gen = 0;
+    ctl->stop = 0;
+    ctl->first_round = ctl->round;
+    ctl->t_start = 0;
 }
 
 // Single-thread epilogue of a round: publish the survivor count to the
 // host-mapped status word and new job completions to the host-mapped ring,
 // advance the round, reset the next queues.
+// Once a round has left no survivors the run is over (stop = kStopDone): the
+// rounds enqueued past it leave the round number and the status word alone,
+// so the host reads the true last round however late it polls.
 __global__ void k_advance(Ctl *ctl, unsigned long long *status_host, const uint32_t *ring, uint32_t ring_cap,
                           uint32_t *ring_host) {
+    if (ctl->stop == kStopDone) return;
     const uint32_t r = ctl->round;
     const uint32_t n_out = ctl->count[(r + 1) % 3] + ctl->solo[(r + 1) % 3];
+    if (n_out == 0 && ring_host == nullptr) ctl->stop = kStopDone;
     ctl->count[(r + 2) % 3] = 0;
     ctl->solo[(r + 2) % 3] = 0;
     ctl->solo_cursor[(r + 1) % 3] = 0;
@@ -1521,7 +1747,10 @@ __global__ void k_advance(Ctl *ctl, unsigned long long *status_host, const uint3
 // Output: follow merge pointers to the representative, write species per
 // sample; representatives insert their species into the job's set.  Counters
 // are summed per wave when the whole wave belongs to one job.
-__global__ void k_resolve(const JobDev *__restrict__ jobs, JobState *js, Lin lin, uint32_t g_begin, uint32_t g_end) {
+// gate (nullable): the control block of a persistent run; nothing is done unless it finished.
+__global__ void k_resolve(const JobDev *__restrict__ jobs, JobState *js, Lin lin, uint32_t g_begin, uint32_t g_end,
+                          const Ctl *gate) {
+    if (gate && gate->stop != kStopDone) return;
     const uint32_t g = g_begin + blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = g < g_end;
     uint32_t jb = 0;
@@ -1897,7 +2126,8 @@ __global__ void k_stream_coal_write(StreamRecs C, const uint32_t *__restrict__ p
 // [j_lo, j_hi) (contiguous in the species-set area, n_slots in all) appends its
 // (species, samples) pair to its job's output.
 __global__ void k_abundance(const JobDev *__restrict__ jobs, JobState *js, uint32_t j_lo, uint32_t j_hi,
-                            uint64_t n_slots) {
+                            uint64_t n_slots, const Ctl *gate) {
+    if (gate && gate->stop != kStopDone) return;
     const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n_slots) return;
     const uint64_t base = jobs[j_lo].rich_off;
@@ -1918,9 +2148,17 @@ __global__ void k_abundance(const JobDev *__restrict__ jobs, JobState *js, uint3
     J->abund_counts_out[at] = J->rich_counts[local];
 }
 
-__global__ void k_finalize(const JobDev *__restrict__ jobs, JobState *js, uint32_t j_begin, uint32_t j_end) {
+// gate as for k_resolve.  mark_failure (enqueue-only calls, which return no
+// status): a job of a run that did not finish, or with a sample id >= N, gets
+// the richness ~0 instead.
+__global__ void k_finalize(const JobDev *__restrict__ jobs, JobState *js, uint32_t j_begin, uint32_t j_end,
+                           const Ctl *gate, uint32_t mark_failure) {
     const uint32_t j = j_begin + blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= j_end) return;
+    if ((gate && gate->stop != kStopDone) || (mark_failure && (js[j].flags & kJobBadSample))) {
+        if (mark_failure && jobs[j].richness_out) *jobs[j].richness_out = ~0ull;
+        return;
+    }
     const bool sentinel = (js[j].flags & kJobSentinelSpecies) != 0u;
     const unsigned long long rich = js[j].rich_count + (sentinel ? 1ull : 0ull);
     js[j].rich_count = rich;
@@ -2260,7 +2498,6 @@ void fill_config(const nh_config *in, nh_config &c) {
     if (c.table_placement > 1) c.table_placement = 0;
     if (!(c.timeout_s > 0)) c.timeout_s = 600.0;
     if (!(c.solo_step > 0)) c.solo_step = 512.0;
-    c.reserved = 0;
 }
 
 std::vector<double> horizon_table(const nh_config &c) {
@@ -2548,6 +2785,213 @@ namespace {
 
 // One device run over many jobs, from the start or (resume) from the state a
 // suspended run left in the workspace.
+// Descriptor of job `job` in a batch run: its species set and counters start
+// at slot rich_off of the run's set area and its lineages at index base; both
+// advance past the job.
+void job_descriptor_run(JobDev &d, const nh_job &job, unsigned long long *rich, uint32_t *rich_counts,
+                        uint64_t &rich_off, uint64_t &base) {
+    const nh_scenario *s = job.scenario;
+    std::memset(&d, 0, sizeof d);
+    d.seed = job.seed;
+    d.nu_thresh = s->nu_thresh;
+    d.inv_lambda = 1.0 / s->lambda;
+    d.dt = s->dt;
+    d.inv_dt = 1.0 / s->dt;
+    d.table = s->d_table;
+    d.row_ptr = s->d_row_ptr;
+    d.cap = s->d_cap;
+    d.prefix = s->d_prefix;
+    d.samples = job.d_sample_ids;
+    d.species_out = (unsigned long long *)job.d_species_out;
+    d.richness_out = (unsigned long long *)job.d_richness_out;
+    const uint64_t slots = pow2_at_least(2 * job.n, 64);
+    d.rich_set = rich + rich_off;
+    d.rich_counts = rich_counts + rich_off;
+    d.rich_off = rich_off;
+    d.rich_mask = (uint32_t)(slots - 1);
+    rich_off += slots;
+    d.spec_loc_out = job.d_spec_loc_out;
+    d.spec_time_out = job.d_spec_time_out;
+    d.abund_ids_out = (unsigned long long *)job.d_abundance_ids_out;
+    d.abund_counts_out = job.d_abundance_counts_out;
+    d.n_individuals = s->N;
+    d.W = s->W;
+    d.H = s->H;
+    d.cmax = s->cmax;
+    d.R = s->R;
+    d.mode = s->mode;
+    d.n_shared = s->n_shared;
+    d.cap_const = s->cap_const;
+    d.caps_in_table = (s->mode == NH_DISPERSAL_PER_DEME && s->cmax <= 0xFFFFu) ? 1u : 0u;
+    d.sampler = s->sampler;
+    d.mu = s->mu;
+    d.p0 = s->p0;
+    d.mig_thresh = s->mig_thresh;
+    d.tau_t = s->tau_t;
+    d.lin_base = (uint32_t)base;
+    d.n = (uint32_t)job.n;
+    d.start_round = 0;
+    base += job.n;
+}
+
+// Per-device resources of persistent runs.  Every persistent run on a device
+// is launched on one library-owned stream, so two grids sized to the whole
+// device are never in flight at once (each would wait at its barriers for
+// workgroups the other keeps out); events join that stream to the caller's
+// stream before and after the launch, so the call stays enqueue-only.
+struct PersistentLane {
+    std::mutex mu;
+    bool ready = false;
+    hipStream_t stream = nullptr;
+    hipEvent_t in = nullptr, out = nullptr;
+    int n_cu = 0, coop = 0, clock_khz = 0;
+};
+
+int persistent_lane(PersistentLane *&out) {
+    static PersistentLane lanes[64];
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(NH_EDEVICE, "device %d is beyond the library's 64", dev);
+    PersistentLane &L = lanes[dev];
+    std::lock_guard<std::mutex> lock(L.mu);
+    if (!L.ready) {
+        HIP_TRY(hipDeviceGetAttribute(&L.n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+        HIP_TRY(hipDeviceGetAttribute(&L.coop, hipDeviceAttributeCooperativeLaunch, dev));
+        HIP_TRY(hipDeviceGetAttribute(&L.clock_khz, hipDeviceAttributeWallClockRate, dev));
+        if (L.clock_khz <= 0) return fail(NH_EDEVICE, "the device reports no wall-clock rate");
+        HIP_TRY(hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&L.in, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&L.out, hipEventDisableTiming));
+        L.ready = true;
+    }
+    out = &L;
+    return NH_OK;
+}
+
+// Round-kernel variants: 0 multi-job, 1 single job, 2 single job with the shared table in LDS.
+const void *run_kernel(uint32_t variant) {
+    if (variant == 2) return reinterpret_cast<const void *>(&k_run<true, true>);
+    if (variant == 1) return reinterpret_cast<const void *>(&k_run<true, false>);
+    return reinterpret_cast<const void *>(&k_run<false, false>);
+}
+
+// Grid of a persistent run: as many workgroups per compute unit as stay
+// resident together (the occupancy of k_run at this block size and LDS), at
+// most cfg.blocks_per_cu.
+int persistent_grid(const PersistentLane &L, uint32_t variant, const nh_config &cfg, size_t lds, uint32_t &grid) {
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, run_kernel(variant), (int)cfg.block_size, lds));
+    per_cu = std::min<int>(per_cu, (int)cfg.blocks_per_cu);
+    if (per_cu < 1) return fail(NH_EINVAL, "no workgroup of %u threads fits a compute unit", cfg.block_size);
+    grid = (uint32_t)(per_cu * L.n_cu);
+    return NH_OK;
+}
+
+// Enqueues a persistent run of the workspace's current state on `stream`:
+// reset the barrier state, then k_run on the device's persistent stream.
+// t0/t1 (nullable) bracket the run kernel alone.
+int enqueue_persistent(PersistentLane &L, uint32_t variant, const RoundArgs &ra, const nh_config &cfg, size_t lds,
+                       uint32_t grid, hipStream_t stream, hipEvent_t t0, hipEvent_t t1) {
+    RunArgs R{};
+    R.max_rounds = cfg.max_rounds;
+    const double khz = (double)L.clock_khz;
+    const double wait_s = cfg.barrier_wait_ms ? cfg.barrier_wait_ms * 1e-3 : std::min(cfg.timeout_s, 60.0);
+    R.spin_ticks = (unsigned long long)std::max(1.0, wait_s * khz * 1e3);
+    R.run_ticks = (unsigned long long)std::max(1.0, cfg.timeout_s * khz * 1e3);
+    RoundArgs a = ra;
+    void *args[] = {&a, &R};
+    std::lock_guard<std::mutex> lock(L.mu);
+    HIP_TRY(hipEventRecord(L.in, stream));
+    HIP_TRY(hipStreamWaitEvent(L.stream, L.in, 0));
+    k_run_reset<<<1, 1, 0, L.stream>>>(ra.ctl);
+    if (t0) HIP_TRY(hipEventRecord(t0, L.stream));
+    if (L.coop)
+        HIP_TRY(hipLaunchCooperativeKernel(run_kernel(variant), dim3(grid), dim3(cfg.block_size), args,
+                                           (unsigned int)lds, L.stream));
+    else
+        HIP_TRY(hipLaunchKernel(run_kernel(variant), dim3(grid), dim3(cfg.block_size), args, lds, L.stream));
+    if (t1) HIP_TRY(hipEventRecord(t1, L.stream));
+    HIP_TRY(hipEventRecord(L.out, L.stream));
+    HIP_TRY(hipStreamWaitEvent(stream, L.out, 0));
+    return NH_OK;
+}
+
+// Round-kernel arguments of a run in workspace ws laid out as L.
+RoundArgs round_args(char *ws, const Workspace &L, uint32_t n_jobs, uint64_t n_total, uint32_t grid,
+                     const nh_config &cfg) {
+    RoundArgs ra;
+    std::memset(&ra, 0, sizeof ra);
+    ra.ctl = (Ctl *)(ws + L.off_ctl);
+    ra.jobs = (JobDev *)(ws + L.off_jobs);
+    ra.js = (JobState *)(ws + L.off_js);
+    ra.ring = (uint32_t *)(ws + L.off_ring);
+    ra.ring_cap = std::max<uint32_t>(n_jobs, 1);
+    ra.lin = lin_view(ws, L);
+    ra.htab = (const double *)(ws + L.off_htab);
+    ra.coop_max = cfg.coop_max ? cfg.coop_max : (uint32_t)(((uint64_t)grid * cfg.block_size) / (2 * kGroup)) + 1;
+    ra.n_cap = (uint32_t)n_total;
+    ra.solo_max = (n_jobs == 1 || grid < 4) ? 0u : cfg.solo_max; // solo blocks never take more than a quarter
+    ra.solo_step = cfg.solo_step;
+    return ra;
+}
+
+// Enqueues a whole single-job run on `stream` in the workspace at ws (at least
+// nh_workspace_bytes(n, 1) bytes): set-up from kernel arguments, lineage init,
+// one persistent round launch and the output kernels, which write the species
+// and the richness only if the run finished and every sample id was valid
+// (else the richness reads ~0).  Nothing waits for the device and nothing is
+// copied from the host.
+int enqueue_single(const nh_scenario *scn, uint64_t seed, const uint64_t *d_samples, uint64_t n,
+                   uint64_t *d_species, uint64_t *d_richness, char *ws, const nh_config &cfg, hipStream_t stream) {
+    const Workspace L = layout(n, 1);
+    PersistentLane *lane = nullptr;
+    if (int rc = persistent_lane(lane)) return rc;
+    const bool lds_table =
+        cfg.table_placement == 0 && scn->mode == NH_DISPERSAL_SHARED && scn->n_shared <= kLdsTableMax;
+    const size_t lds_bytes = lds_table ? sizeof(uint4) * scn->n_shared : 0;
+    const uint32_t variant = lds_table ? 2u : 1u;
+    uint32_t grid = 0;
+    if (int rc = persistent_grid(*lane, variant, cfg, lds_bytes, grid)) return rc;
+    const RoundArgs ra = round_args(ws, L, 1, n, grid, cfg);
+    unsigned long long *rich = (unsigned long long *)(ws + L.off_rich);
+    uint32_t *rich_counts = (uint32_t *)(ws + L.off_rcount);
+    const nh_job job{scn, seed, d_samples, n, d_species, d_richness, nullptr, nullptr, nullptr, nullptr};
+    JobDev jd;
+    uint64_t rich_off = 0, base = 0;
+    job_descriptor_run(jd, job, rich, rich_counts, rich_off, base);
+    JobDev *d_jobs = (JobDev *)ra.jobs;
+    k_setup_single<<<1, 64, 0, stream>>>(ra.ctl, ra.js, d_jobs, jd, (double *)ra.htab, cfg.horizon0,
+                                         cfg.horizon_growth, cfg.horizon_step_max);
+    k_fill_u64<<<1024, 256, 0, stream>>>(ra.lin.hash, L.hcap, 0ull);
+    k_fill_u64<<<1024, 256, 0, stream>>>(rich, rich_off, ~0ull);
+    k_fill_u64<<<1024, 256, 0, stream>>>((unsigned long long *)rich_counts, rich_off / 2, 0ull);
+    if (n) {
+        const uint32_t blocks = (uint32_t)((n + 255) / 256);
+        k_init<<<blocks, 256, 0, stream>>>(ra.ctl, d_jobs, 1, 0, ra.js, ra.ring, ra.ring_cap, ra.lin, 0,
+                                           (uint32_t)n);
+        HIP_TRY(hipGetLastError());
+        if (int rc = enqueue_persistent(*lane, variant, ra, cfg, lds_bytes, grid, stream, nullptr, nullptr))
+            return rc;
+        k_resolve<<<blocks, 256, 0, stream>>>(d_jobs, ra.js, ra.lin, 0, (uint32_t)n, ra.ctl);
+    }
+    k_finalize<<<1, 64, 0, stream>>>(d_jobs, ra.js, 0, 1, n ? ra.ctl : nullptr, 1u);
+    HIP_TRY(hipGetLastError());
+    return NH_OK;
+}
+
+// Checks of an enqueue-only single-job call that need no device access.
+int check_single(const nh_scenario *scn, const uint64_t *d_samples, uint64_t n, const uint64_t *d_species,
+                 const nh_config &cfg) {
+    if (!scn) return fail(NH_EINVAL, "scenario is NULL");
+    if (n > 0 && (!d_samples || !d_species)) return fail(NH_EINVAL, "NULL sample or output buffer");
+    if (n >= (1ull << 31)) return fail(NH_EINVAL, "more than 2^31 - 1 samples in one run");
+    if (cfg.block_size % 64 != 0 || cfg.block_size > 256)
+        return fail(NH_EINVAL, "block_size must be a multiple of 64 up to 256");
+    if (cfg.launch != NH_LAUNCH_PERSISTENT) return fail(NH_EINVAL, "enqueue-only runs are persistent launches");
+    if (cfg.max_rounds != 0) return fail(NH_EINVAL, "enqueue-only runs cannot suspend (max_rounds must be 0)");
+    return NH_OK;
+}
+
 int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint64_t workspace_bytes,
                    const nh_config *cfg_in, nh_stats *stats, void *stream_ptr, bool resume) {
     using clock = std::chrono::steady_clock;
@@ -2590,55 +3034,10 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
     std::vector<JobDev> hj(n_jobs);
     uint64_t base = 0, rich_off = 0;
     bool any_abundance = false;
-    bool all_same_scenario = true;
     for (uint32_t j = 0; j < n_jobs; ++j) {
-        const nh_scenario *s = jobs[j].scenario;
-        if (s != jobs[0].scenario) all_same_scenario = false;
-        JobDev &d = hj[j];
-        std::memset(&d, 0, sizeof d);
-        d.seed = jobs[j].seed;
-        d.nu_thresh = s->nu_thresh;
-        d.inv_lambda = 1.0 / s->lambda;
-        d.dt = s->dt;
-        d.inv_dt = 1.0 / s->dt;
-        d.table = s->d_table;
-        d.row_ptr = s->d_row_ptr;
-        d.cap = s->d_cap;
-        d.prefix = s->d_prefix;
-        d.samples = jobs[j].d_sample_ids;
-        d.species_out = (unsigned long long *)jobs[j].d_species_out;
-        d.richness_out = (unsigned long long *)jobs[j].d_richness_out;
-        const uint64_t slots = pow2_at_least(2 * jobs[j].n, 64);
-        d.rich_set = rich + rich_off;
-        d.rich_counts = rich_counts + rich_off;
-        d.rich_off = rich_off;
-        d.rich_mask = (uint32_t)(slots - 1);
-        rich_off += slots;
-        d.spec_loc_out = jobs[j].d_spec_loc_out;
-        d.spec_time_out = jobs[j].d_spec_time_out;
-        d.abund_ids_out = (unsigned long long *)jobs[j].d_abundance_ids_out;
-        d.abund_counts_out = jobs[j].d_abundance_counts_out;
-        if (d.abund_counts_out) any_abundance = true;
-        d.n_individuals = s->N;
-        d.W = s->W;
-        d.H = s->H;
-        d.cmax = s->cmax;
-        d.R = s->R;
-        d.mode = s->mode;
-        d.n_shared = s->n_shared;
-        d.cap_const = s->cap_const;
-        d.caps_in_table = (s->mode == NH_DISPERSAL_PER_DEME && s->cmax <= 0xFFFFu) ? 1u : 0u;
-        d.sampler = s->sampler;
-        d.mu = s->mu;
-        d.p0 = s->p0;
-        d.mig_thresh = s->mig_thresh;
-        d.tau_t = s->tau_t;
-        d.lin_base = (uint32_t)base;
-        d.n = (uint32_t)jobs[j].n;
-        d.start_round = 0;
-        base += jobs[j].n;
+        job_descriptor_run(hj[j], jobs[j], rich, rich_counts, rich_off, base);
+        if (hj[j].abund_counts_out) any_abundance = true;
     }
-    (void)all_same_scenario;
     const std::vector<double> htab = horizon_table(cfg);
 
     PinnedStatus st;
@@ -2690,9 +3089,21 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
     // The status word: round 0 and "not finished" until the first round kernel reports.
     __atomic_store_n(st.host, (unsigned long long)1, __ATOMIC_SEQ_CST);
 
-    // Round kernels: replayed from a captured graph of cfg.rounds_per_graph launches.
-    const uint32_t grid = (uint32_t)std::max(1, n_cu) * cfg.blocks_per_cu;
+    // Round kernels: one persistent launch, or replayed from a captured graph of
+    // cfg.rounds_per_graph launches.
     const bool single = n_jobs == 1;
+    const nh_scenario *s0 = jobs[0].scenario;
+    const bool lds_table =
+        single && cfg.table_placement == 0 && s0->mode == NH_DISPERSAL_SHARED && s0->n_shared <= kLdsTableMax;
+    const size_t lds_bytes = lds_table ? sizeof(uint4) * s0->n_shared : 0;
+    const uint32_t variant = lds_table ? 2u : (single ? 1u : 0u);
+    const bool persistent = cfg.launch == NH_LAUNCH_PERSISTENT;
+    PersistentLane *lane = nullptr;
+    uint32_t grid = (uint32_t)std::max(1, n_cu) * cfg.blocks_per_cu;
+    if (persistent) {
+        if (int rc = persistent_lane(lane)) return rc;
+        if (int rc = persistent_grid(*lane, variant, cfg, lds_bytes, grid)) return rc;
+    }
     RoundArgs ra;
     std::memset(&ra, 0, sizeof ra);
     ra.ctl = ctl;
@@ -2706,10 +3117,6 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
     ra.n_cap = (uint32_t)n_total;
     ra.solo_max = (single || grid < 4) ? 0u : cfg.solo_max; // solo blocks never take more than a quarter
     ra.solo_step = cfg.solo_step;
-    const nh_scenario *s0 = jobs[0].scenario;
-    const bool lds_table =
-        single && cfg.table_placement == 0 && s0->mode == NH_DISPERSAL_SHARED && s0->n_shared <= kLdsTableMax;
-    const size_t lds_bytes = lds_table ? sizeof(uint4) * s0->n_shared : 0;
     auto launch_round = [&](hipStream_t s) {
         if (lds_table)
             k_round<true, true><<<grid, cfg.block_size, lds_bytes, s>>>(ra);
@@ -2732,8 +3139,7 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
     };
     thread_local std::vector<GraphEntry> graph_cache;
     hipGraphExec_t exec = nullptr;
-    bool use_graph = cfg.rounds_per_graph > 1;
-    const uint32_t variant = lds_table ? 2u : (single ? 1u : 0u);
+    bool use_graph = !persistent && cfg.rounds_per_graph > 1;
     if (use_graph && n_total) {
         for (auto &ge : graph_cache) {
             if (ge.grid == grid && ge.block == cfg.block_size && ge.rounds == cfg.rounds_per_graph &&
@@ -2799,7 +3205,28 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
     const auto t_start = clock::now();
     uint32_t final_round = base_round - 1;
     bool suspended = false;
-    if (n_total) {
+    if (persistent && n_total) {
+        // One launch runs every round; the output kernels run only if it finished (the control
+        // block says so), so nothing here waits for the device.
+        hipEvent_t t0 = nullptr, t1 = nullptr;
+        if (cfg.event_timing) {
+            while (ev_pool.size() < 2) {
+                hipEvent_t e;
+                HIP_TRY(hipEventCreate(&e));
+                ev_pool.push_back(e);
+            }
+            t0 = ev_pool[0];
+            t1 = ev_pool[1];
+            ev_used = 1;
+        }
+        if (int rc = enqueue_persistent(*lane, variant, ra, cfg, lds_bytes, grid, stream, t0, t1)) return rc;
+        const uint32_t blocks = (uint32_t)((n_total + 255) / 256);
+        k_resolve<<<blocks, 256, 0, stream>>>(d_jobs, d_js, lin, 0, (uint32_t)n_total, ctl);
+        if (any_abundance)
+            k_abundance<<<(uint32_t)((rich_off + 255) / 256), 256, 0, stream>>>(d_jobs, d_js, 0, n_jobs, rich_off,
+                                                                                ctl);
+        k_finalize<<<(n_jobs + 255) / 256, 256, 0, stream>>>(d_jobs, d_js, 0, n_jobs, ctl, 0u);
+    } else if (n_total) {
         // Keep two launches in flight; stop when a round reports an empty queue, or, past
         // cfg.max_rounds, once every enqueued round has run.  Whatever is enqueued past the
         // last round still runs (two near-empty launches per round, about 9 us), which is
@@ -2849,13 +3276,14 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
         }
         if (!suspended) {
             const uint32_t blocks = (uint32_t)((n_total + 255) / 256);
-            k_resolve<<<blocks, 256, 0, stream>>>(d_jobs, d_js, lin, 0, (uint32_t)n_total);
+            k_resolve<<<blocks, 256, 0, stream>>>(d_jobs, d_js, lin, 0, (uint32_t)n_total, nullptr);
             if (any_abundance)
                 k_abundance<<<(uint32_t)((rich_off + 255) / 256), 256, 0, stream>>>(d_jobs, d_js, 0, n_jobs,
-                                                                                    rich_off);
+                                                                                    rich_off, nullptr);
         }
     }
-    if (!suspended) k_finalize<<<(n_jobs + 255) / 256, 256, 0, stream>>>(d_jobs, d_js, 0, n_jobs);
+    if (!suspended && !(persistent && n_total))
+        k_finalize<<<(n_jobs + 255) / 256, 256, 0, stream>>>(d_jobs, d_js, 0, n_jobs, nullptr, 0u);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(ev1, stream));
     std::vector<JobState> hs(n_jobs);
@@ -2863,6 +3291,17 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
     HIP_TRY(hipMemcpyAsync(hs.data(), d_js, sizeof(JobState) * n_jobs, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipMemcpyAsync(&hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
+    if (persistent && n_total) {
+        if (hctl.error & kErrTimeout)
+            return fail(NH_ETIMEOUT, "run exceeded %.1f s (round %u)", cfg.timeout_s, hctl.round);
+        if (hctl.error & kErrStall)
+            return fail(NH_EDEVICE, "a grid barrier wait exceeded its limit (round %u)", hctl.round);
+        if (hctl.stop != kStopDone && hctl.stop != kStopSuspended && hctl.error == 0)
+            return fail(NH_EDEVICE, "the persistent run ended in state %u", hctl.stop);
+        suspended = hctl.stop == kStopSuspended;
+        final_round = hctl.round - 1;
+        rounds_enqueued = 1; // one round-kernel launch
+    }
     if (hctl.error & kErrBadSample) return fail(NH_EINVAL, "a sample id is not below the number of individuals");
     if (hctl.error) return fail(NH_EDEVICE, "kernel reported error flags 0x%x", hctl.error);
     float ms = 0.f;
@@ -3176,6 +3615,25 @@ NH_API int nh_simulate_device(const nh_scenario *scenario, uint64_t seed, const 
     return rc;
 }
 
+NH_API int nh_simulate_async(const nh_scenario *scenario, uint64_t seed, const uint64_t *d_sample_ids, uint64_t n,
+                             uint64_t *d_species_out, uint64_t *d_richness_out, const nh_config *cfg_in,
+                             void *stream_ptr) {
+    nh_config cfg;
+    fill_config(cfg_in, cfg);
+    if (int rc = check_single(scenario, d_sample_ids, n, d_species_out, cfg)) return rc;
+    hipStream_t stream = (hipStream_t)stream_ptr;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    const uint64_t bytes = nh_workspace_bytes(n, 1);
+    void *ws = nullptr;
+    if (hipMemPool_t pool = scratch_pool(dev)) HIP_TRY(hipMallocFromPoolAsync(&ws, bytes, pool, stream));
+    else HIP_TRY(hipMallocAsync(&ws, bytes, stream));
+    const int rc = enqueue_single(scenario, seed, d_sample_ids, n, d_species_out, d_richness_out, (char *)ws, cfg,
+                                  stream);
+    (void)hipFreeAsync(ws, stream);
+    return rc;
+}
+
 NH_API int nh_simulate(const nh_scenario *scenario, uint64_t seed, const uint64_t *h_sample_ids, uint64_t n,
                        uint64_t *h_species_out, uint64_t *h_richness_out, nh_stats *stats) {
     if (!scenario) return fail(NH_EINVAL, "scenario is NULL");
@@ -3398,7 +3856,7 @@ int server_admit(nh_server *s, const nh_job &job, uint64_t tag, bool &admitted) 
                                                s->max_jobs, s->lin, (uint32_t)lin_at, (uint32_t)(lin_at + job.n));
     } else {
         // nothing to simulate: resolve (richness 0) right away
-        k_finalize<<<1, 1, 0, s->stream>>>(s->d_jobs, s->d_js, slot, slot + 1);
+        k_finalize<<<1, 1, 0, s->stream>>>(s->d_jobs, s->d_js, slot, slot + 1, nullptr, 0u);
         HIP_TRY(hipMemcpyAsync(&s->js_h[slot], &s->d_js[slot], sizeof(JobState), hipMemcpyDeviceToHost, s->stream));
         HIP_TRY(hipEventRecord(sl.ev, s->stream));
         sl.state = kSlotResolving;
@@ -3571,11 +4029,11 @@ NH_API int nh_server_progress(nh_server *s, uint32_t *active_out, uint32_t *pend
         ServerSlot &sl = s->slots[slot];
         const uint32_t blocks = (uint32_t)((sl.n + 255) / 256);
         k_resolve<<<blocks, 256, 0, s->stream>>>(s->d_jobs, s->d_js, s->lin, (uint32_t)sl.lin_base,
-                                                  (uint32_t)(sl.lin_base + sl.n));
+                                                  (uint32_t)(sl.lin_base + sl.n), nullptr);
         if (sl.job.d_abundance_counts_out)
             k_abundance<<<(uint32_t)((sl.rich_slots + 255) / 256), 256, 0, s->stream>>>(s->d_jobs, s->d_js, slot,
-                                                                                      slot + 1, sl.rich_slots);
-        k_finalize<<<1, 1, 0, s->stream>>>(s->d_jobs, s->d_js, slot, slot + 1);
+                                                                                      slot + 1, sl.rich_slots, nullptr);
+        k_finalize<<<1, 1, 0, s->stream>>>(s->d_jobs, s->d_js, slot, slot + 1, nullptr, 0u);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(&s->js_h[slot], &s->d_js[slot], sizeof(JobState), hipMemcpyDeviceToHost, s->stream));
         HIP_TRY(hipEventRecord(sl.ev, s->stream));

@@ -217,8 +217,10 @@ def test_event_stream_of_the_256_torus(B, torch_mod):
 
 
 @pytest.mark.parametrize("knobs", [dict(), dict(horizon0=2.0, horizon_growth=2.0),
-                                   dict(horizon0=0.25, horizon_growth=1.5, horizon_step_max=16.0)],
-                         ids=["default", "2x2", "capped"])
+                                   dict(horizon0=0.25, horizon_growth=1.5, horizon_step_max=16.0),
+                                   dict(launch=1), dict(launch=1, horizon0=0.25, horizon_growth=1.5,
+                                                        horizon_step_max=16.0)],
+                         ids=["default", "2x2", "capped", "graphs", "graphs-capped"])
 def test_one_round_per_horizon_window(B, torch_mod, knobs):
     """A single-job run takes one round per horizon window up to the window of its last event,
     with the horizons bench.py derives from the config, so the per-window maxima it reports

@@ -120,10 +120,11 @@ def test_small_workloads_full(B, wl):
     scn = B.Scenario.from_workload(wl)
     d_s = torch.from_numpy(samples.astype(np.int64)).to(dev)
     ws = torch.empty(B.workspace_bytes(len(samples), 1), dtype=torch.uint8, device=dev)
-    for coop in (1 << 30, 1):
+    for coop, launch in ((1 << 30, B.NH_LAUNCH_PERSISTENT), (1, B.NH_LAUNCH_PERSISTENT),
+                         (1 << 30, B.NH_LAUNCH_GRAPHS), (1, B.NH_LAUNCH_GRAPHS)):
         out = torch.empty(len(samples), dtype=torch.int64, device=dev)
-        st2 = B.batch_run([(scn, seed, d_s, out, None)], ws, B.make_config(coop_max=coop))[0]
-        assert np.array_equal(out.cpu().numpy().view(np.uint64), ref), coop
+        st2 = B.batch_run([(scn, seed, d_s, out, None)], ws, B.make_config(coop_max=coop, launch=launch))[0]
+        assert np.array_equal(out.cpu().numpy().view(np.uint64), ref), (coop, launch)
         assert st2["events"] == st["events"] or coop == 1
 
 
@@ -209,7 +210,9 @@ def test_tuning_never_changes_results(B, torch_mod):
     for cfg in (dict(), dict(horizon0=0.125, horizon_growth=1.05), dict(horizon0=8.0, horizon_growth=2.0),
                 dict(block_size=64, blocks_per_cu=1, rounds_per_graph=1), dict(block_size=128, blocks_per_cu=8),
                 dict(horizon_step_max=1.0, rounds_per_graph=32), dict(coop_max=1), dict(coop_max=1 << 30),
-                dict(coop_max=1 << 30, block_size=64, horizon0=2.0)):
+                dict(coop_max=1 << 30, block_size=64, horizon0=2.0), dict(launch=B.NH_LAUNCH_GRAPHS),
+                dict(launch=B.NH_LAUNCH_GRAPHS, block_size=64, blocks_per_cu=1, rounds_per_graph=1),
+                dict(launch=B.NH_LAUNCH_GRAPHS, horizon_step_max=1.0, rounds_per_graph=32)):
         say("config 2 tuning", cfg)
         out = torch.empty(len(wl.samples), dtype=torch.int64, device=dev)
         B.batch_run([(scn, 42, samples, out, None)], ws, B.make_config(**cfg))
@@ -341,12 +344,14 @@ def test_solo_tails_never_change_results(B, torch_mod):
                 assert np.array_equal(a, b)
 
 
-def test_checkpoint_resume_equals_uninterrupted(B, torch_mod):
+@pytest.mark.parametrize("launch", [0, 1], ids=["persistent", "graphs"])
+def test_checkpoint_resume_equals_uninterrupted(B, torch_mod, launch):
     """A run suspended between rounds, its workspace copied to the host, the device copy destroyed
     and the bytes restored (in place, then into another buffer) finishes with bitwise the same ids,
     richness and event counts as an uninterrupted run; a multi-job batch also resumes under other
-    tuning knobs."""
+    tuning knobs (and the other launch form)."""
     torch = torch_mod
+    mk = lambda **kw: B.make_config(launch=launch, **kw)  # noqa: E731
     dev = torch.device("cuda:0")
     wl = W.config2()
     scn = B.Scenario.from_workload(wl)
@@ -356,12 +361,12 @@ def test_checkpoint_resume_equals_uninterrupted(B, torch_mod):
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     ref = torch.empty(n, dtype=torch.int64, device=dev)
     rich_ref = torch.zeros(1, dtype=torch.int64, device=dev)
-    st_ref = B.batch_run([(scn, 42, s, ref, rich_ref)], ws)[0]
+    st_ref = B.batch_run([(scn, 42, s, ref, rich_ref)], ws, mk())[0]
     assert not st_ref["suspended"]
     out = torch.empty(n, dtype=torch.int64, device=dev)
     rich = torch.zeros(1, dtype=torch.int64, device=dev)
     job = [(scn, 42, s, out, rich)]
-    cap = B.make_config(max_rounds=3)
+    cap = mk(max_rounds=3)
     st = B.batch_run(job, ws, cap)[0]
     say("checkpoint: suspended after", st["rounds"], "rounds")
     assert st["suspended"] and 3 <= st["rounds"] < st_ref["rounds"]
@@ -375,7 +380,7 @@ def test_checkpoint_resume_equals_uninterrupted(B, torch_mod):
     ws2 = torch.empty(nbytes + 512, dtype=torch.uint8, device=dev)[256:256 + nbytes]  # another buffer
     assert ws2.data_ptr() != ws.data_ptr() and ws2.data_ptr() % 256 == 0
     ws2.copy_(host.to(dev))
-    st = B.batch_resume(job, ws2)[0]
+    st = B.batch_resume(job, ws2, mk())[0]
     assert not st["suspended"] and st["rounds"] == st_ref["rounds"]
     torch.cuda.synchronize()
     assert torch.equal(out, ref) and int(rich.item()) == int(rich_ref.item())
@@ -393,15 +398,16 @@ def test_checkpoint_resume_equals_uninterrupted(B, torch_mod):
     B.batch_run([(scns[k], wls[k].seeds[0], ss[k], outs_a[k], None) for k in range(len(wls))], wsb)
     outs_b = [torch.empty(len(w.samples), dtype=torch.int64, device=dev) for w in wls]
     jobs_b = [(scns[k], wls[k].seeds[0], ss[k], outs_b[k], None) for k in range(len(wls))]
-    st = B.batch_run(jobs_b, wsb, B.make_config(max_rounds=5, rounds_per_graph=1))
+    st = B.batch_run(jobs_b, wsb, mk(max_rounds=5, rounds_per_graph=1))
     assert st[0]["suspended"]
-    st = B.batch_resume(jobs_b, wsb, B.make_config(block_size=128, blocks_per_cu=2, solo_max=64))
+    st = B.batch_resume(jobs_b, wsb, B.make_config(block_size=128, blocks_per_cu=2, solo_max=64, launch=1 - launch))
     assert not st[0]["suspended"]
     for a, b in zip(outs_a, outs_b):
         assert torch.equal(a, b)
 
 
-def test_timed_out_run_fails_cleanly_and_reruns_bitwise(B, torch_mod):
+@pytest.mark.parametrize("launch", [0, 1], ids=["persistent", "graphs"])
+def test_timed_out_run_fails_cleanly_and_reruns_bitwise(B, torch_mod, launch):
     """A run stopped by its wall-clock limit (forced from the host: every kernel still finishes its
     round) reports NH_ETIMEOUT; the same call afterwards gives the uninterrupted result."""
     torch = torch_mod
@@ -413,8 +419,28 @@ def test_timed_out_run_fails_cleanly_and_reruns_bitwise(B, torch_mod):
     ws = torch.empty(B.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
     out = torch.empty(n, dtype=torch.int64, device=dev)
     with pytest.raises(B.NecsimError) as e:
-        B.batch_run([(scn, 9, s, out, None)], ws, B.make_config(timeout_s=1e-9))
+        B.batch_run([(scn, 9, s, out, None)], ws, B.make_config(timeout_s=1e-9, launch=launch))
     assert e.value.code == B.NH_ETIMEOUT
+    B.batch_run([(scn, 9, s, out, None)], ws, B.make_config(launch=launch))
+    ref, _, _ = B.simulate(scn, 9, wl.samples)
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), ref)
+
+
+def test_barrier_wait_limit_stops_the_run_and_the_kernel_exits(B, torch_mod):
+    """A persistent run whose grid barrier wait limit is shorter than a round (forced from the host: a
+    first horizon past the whole run makes one round of several milliseconds, the limit is 1 ms)
+    stops with NH_EDEVICE; every workgroup leaves, and the next call gives the normal result."""
+    torch = torch_mod
+    dev = torch.device("cuda:0")
+    wl = W.config2()
+    scn = B.Scenario.from_workload(wl)
+    n = len(wl.samples)
+    s = torch.from_numpy(wl.samples.astype(np.int64)).to(dev)
+    ws = torch.empty(B.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
+    out = torch.empty(n, dtype=torch.int64, device=dev)
+    with pytest.raises(B.NecsimError) as e:
+        B.batch_run([(scn, 9, s, out, None)], ws, B.make_config(horizon0=1e7, coop_max=1, barrier_wait_ms=1))
+    assert e.value.code == B.NH_EDEVICE and "barrier" in str(e.value)
     B.batch_run([(scn, 9, s, out, None)], ws)
     ref, _, _ = B.simulate(scn, 9, wl.samples)
     assert np.array_equal(out.cpu().numpy().view(np.uint64), ref)
