@@ -135,6 +135,26 @@ struct JobState {
     uint32_t sentinel_count; // samples whose species id equals the set's empty marker
 };
 
+// One counter of the persistent run's two-level grid barrier, on a cache line
+// of its own: arrivals at the current barrier, barriers completed, and the
+// next round's control words (round, main queue, solo queue, stop) published
+// with the release so a waiter reads them from the line it polled.
+constexpr uint32_t kBarGroup = 32;     // workgroups per first-level counter
+constexpr uint32_t kMaxBarGroups = 64; // persistent grids up to 2048 workgroups
+struct alignas(128) BarSlot {
+    uint32_t arrived;
+    uint32_t gen;
+    uint32_t pub[4];
+};
+
+// Op counts of a run (Philox blocks evaluated in all domains, exponential
+// waiting-time draws), spread over lines so that workgroups finishing together
+// do not queue on one address.
+constexpr uint32_t kOpSlots = 32;
+struct alignas(128) OpSlot {
+    unsigned long long philox, draws;
+};
+
 // Run control block (device memory, inside the workspace).
 struct Ctl {
     uint32_t round;      // round the next round kernel runs
@@ -147,14 +167,13 @@ struct Ctl {
     uint32_t n_jobs;
     uint32_t ring_head;  // completions pushed (job slots whose lineages are all retired)
     uint32_t ring_pub;   // completions already copied to the host-mapped ring
-    unsigned long long philox_calls; // Philox blocks evaluated (all domains)
-    unsigned long long exp_draws;    // exponential waiting-time draws (logarithms)
+    OpSlot ops[kOpSlots];            // op counts, summed over the slots: workgroup b adds to slot b % kOpSlots
     // Persistent runs (k_run): grid barrier and stop state, reset before every launch.
-    uint32_t bar_arrived;            // workgroups arrived at the current barrier
-    uint32_t bar_gen;                // barriers completed
     uint32_t stop;                   // kStop*: why the run ended (0: running)
     uint32_t first_round;            // round the launch started with
     unsigned long long t_start;      // device wall clock when the launch started
+    BarSlot top;                     // second barrier level: one arrival per group of workgroups
+    BarSlot grp[kMaxBarGroups];      // first level: kBarGroup workgroups each
 };
 
 // Why a persistent run ended.
@@ -633,23 +652,28 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
 
 // Op counters: per-wave sums go to LDS, one global atomic per workgroup.
 // Every thread of the block must call it.
-__device__ __forceinline__ void flush_counters_block(Ctl *ctl, const Counters &c) {
+__device__ __forceinline__ void flush_counters_block(Ctl *ctl, unsigned long long philox, unsigned long long draws) {
     __shared__ unsigned long long acc[2];
     if (threadIdx.x == 0) {
         acc[0] = 0;
         acc[1] = 0;
     }
     __syncthreads();
-    const unsigned long long ph = wave_sum(c.philox), dr = wave_sum(c.draws);
+    const unsigned long long ph = wave_sum(philox), dr = wave_sum(draws);
     if (lane_id() == 0 && (ph | dr)) {
         atomicAdd(&acc[0], ph);
         atomicAdd(&acc[1], dr);
     }
     __syncthreads();
     if (threadIdx.x == 0 && (acc[0] | acc[1])) {
-        atomicAdd(&ctl->philox_calls, acc[0]);
-        atomicAdd(&ctl->exp_draws, acc[1]);
+        OpSlot &o = ctl->ops[blockIdx.x % kOpSlots];
+        atomicAdd(&o.philox, acc[0]);
+        atomicAdd(&o.draws, acc[1]);
     }
+}
+
+__device__ __forceinline__ void flush_counters_block(Ctl *ctl, const Counters &c) {
+    flush_counters_block(ctl, (unsigned long long)c.philox, (unsigned long long)c.draws);
 }
 
 __device__ __forceinline__ uint32_t wave_reserve(uint64_t mask, uint32_t *counter) {
@@ -945,12 +969,9 @@ __global__ void k_setup(Ctl *ctl, JobState *js, const JobDev *jobs, uint32_t n_j
         ctl->blocks_done = 0;
         ctl->error = 0;
         ctl->n_jobs = n_jobs;
-        ctl->philox_calls = 0;
-        ctl->exp_draws = 0;
+        for (uint32_t k = 0; k < kOpSlots; ++k) ctl->ops[k] = OpSlot{};
         ctl->ring_head = 0;
         ctl->ring_pub = 0;
-        ctl->bar_arrived = 0;
-        ctl->bar_gen = 0;
         ctl->stop = 0;
         ctl->first_round = first_round;
         ctl->t_start = 0;
@@ -992,12 +1013,9 @@ __global__ void k_setup_single(Ctl *ctl, JobState *js, JobDev *jobs, JobDev job,
     ctl->blocks_done = 0;
     ctl->error = 0;
     ctl->n_jobs = 1;
-    ctl->philox_calls = 0;
-    ctl->exp_draws = 0;
+    for (uint32_t k = 0; k < kOpSlots; ++k) ctl->ops[k] = OpSlot{};
     ctl->ring_head = 0;
     ctl->ring_pub = 0;
-    ctl->bar_arrived = 0;
-    ctl->bar_gen = 0;
     ctl->stop = 0;
     ctl->first_round = 1;
     ctl->t_start = 0;
@@ -1595,13 +1613,20 @@ struct RoundCtl {
     uint32_t r, n_main, n_solo, stop;
 };
 
-// The round control words as the last epilogue left them (agent-scope loads).
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t *p, uint32_t x) {
+    __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The round control words as the host-side set-up left them (launch start).
 __device__ __forceinline__ RoundCtl read_round_ctl(Ctl *ctl, bool single) {
     RoundCtl c;
-    c.r = __hip_atomic_load(&ctl->round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    c.n_main = __hip_atomic_load(&ctl->count[c.r % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    c.n_solo = single ? 0u : __hip_atomic_load(&ctl->solo[c.r % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    c.stop = __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    c.r = ld_agent(&ctl->round);
+    c.n_main = ld_agent(&ctl->count[c.r % 3]);
+    c.n_solo = single ? 0u : ld_agent(&ctl->solo[c.r % 3]);
+    c.stop = ld_agent(&ctl->stop);
     return c;
 }
 
@@ -1611,68 +1636,114 @@ __device__ __forceinline__ unsigned long long run_start(Ctl *ctl) {
 }
 
 // Round epilogue of a persistent run (one thread, after every workgroup has
-// finished round r): the same bookkeeping as k_advance, then the stop decision.
-__device__ __forceinline__ void run_epilogue(Ctl *ctl, const RunArgs &R) {
-    auto ld = [](uint32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
-    auto st = [](uint32_t *p, uint32_t x) { __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
-    const uint32_t r = ld(&ctl->round);
-    const uint32_t n_out = ld(&ctl->count[(r + 1) % 3]) + ld(&ctl->solo[(r + 1) % 3]);
-    st(&ctl->count[(r + 2) % 3], 0u);
-    st(&ctl->solo[(r + 2) % 3], 0u);
-    st(&ctl->solo_cursor[(r + 1) % 3], 0u);
-    st(&ctl->cursor[(r + 1) % 3], 0u);
-    st(&ctl->round, r + 1);
+// finished round r): the same bookkeeping as k_advance, then the stop
+// decision; returns the next round's control words.
+__device__ __forceinline__ RoundCtl run_epilogue(Ctl *ctl, const RunArgs &R) {
+    const uint32_t r = ld_agent(&ctl->round);
+    // independent loads (the queue words of every slot), selected afterwards
+    uint32_t cnt[3], solo[3];
+    for (int k = 0; k < 3; ++k) {
+        cnt[k] = ld_agent(&ctl->count[k]);
+        solo[k] = ld_agent(&ctl->solo[k]);
+    }
+    const uint32_t err = ld_agent(&ctl->error), first = ld_agent(&ctl->first_round);
+    const uint32_t q = (r + 1) % 3;
+    const uint32_t n_out = cnt[q] + solo[q];
+    st_agent(&ctl->count[(r + 2) % 3], 0u);
+    st_agent(&ctl->solo[(r + 2) % 3], 0u);
+    st_agent(&ctl->solo_cursor[q], 0u);
+    st_agent(&ctl->cursor[q], 0u);
+    st_agent(&ctl->round, r + 1);
     uint32_t stop = 0;
     if (n_out == 0) {
         stop = kStopDone;
-    } else if ((ld(&ctl->error) & ~kErrBadSample) != 0u) {
+    } else if ((err & ~kErrBadSample) != 0u) {
         stop = kStopError; // a bad sample id only fails its own job
-    } else if (R.max_rounds != 0u && r + 1u - ld(&ctl->first_round) >= R.max_rounds) {
+    } else if (R.max_rounds != 0u && r + 1u - first >= R.max_rounds) {
         stop = kStopSuspended;
     } else if (wall_clock64() - run_start(ctl) > R.run_ticks) {
         atomicOr(&ctl->error, kErrTimeout);
         stop = kStopError;
     }
-    if (stop) atomicCAS(&ctl->stop, 0u, stop); // a workgroup that gave up waiting has stopped the run already
+    // a workgroup that gave up waiting has stopped the run already (if it has and the run goes on,
+    // the workgroups learn it in their next wait)
+    if (stop) {
+        const uint32_t old = atomicCAS(&ctl->stop, 0u, stop);
+        if (old != 0u) stop = old;
+    }
+    return RoundCtl{r + 1, cnt[q], solo[q], stop};
 }
 
-// Grid barrier between rounds.  Every workgroup calls it with the same gen
-// (barriers passed so far); the last to arrive runs the epilogue and releases
-// the others.  A wait is bounded: past R.spin_ticks, or once the run has been
-// stopped, a workgroup stops waiting, flags the run and leaves, and the round
-// loop then ends every workgroup.  On return the workgroup's copy of the
-// round control (sc) is current.
-__device__ __forceinline__ void grid_sync(Ctl *ctl, const RunArgs &R, uint32_t &gen, RoundCtl &sc, bool single) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence(); // release this workgroup's writes of the round (agent scope)
-        const uint32_t arrived = atomicAdd(&ctl->bar_arrived, 1u);
-        if (arrived == gridDim.x - 1u) {
-            __threadfence(); // acquire every workgroup's writes
-            __hip_atomic_store(&ctl->bar_arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            run_epilogue(ctl, R);
-            __hip_atomic_store(&ctl->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            const unsigned long long t0 = wall_clock64();
-            // relaxed loads while waiting (an acquire per poll would invalidate the L2 each time)
-            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                if (__hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
-                const unsigned long long now = wall_clock64();
-                // past the run's own time limit the run has timed out; otherwise a wait this long
-                // means workgroups that never arrive
-                const bool late = now - run_start(ctl) > R.run_ticks;
-                if (late || now - t0 > R.spin_ticks) {
-                    atomicOr(&ctl->error, late ? kErrTimeout : kErrStall);
-                    __hip_atomic_store(&ctl->stop, kStopError, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
+// Waits (one thread) until *gen moves past `seen`, the run stops, or a limit
+// passes: past the run's own time limit the run has timed out; otherwise a
+// wait longer than R.spin_ticks means workgroups that never arrive.  Returns
+// false if it gave up (and has stopped the run).
+__device__ __forceinline__ bool wait_gen(Ctl *ctl, const RunArgs &R, const uint32_t *gen, uint32_t seen) {
+    const unsigned long long t0 = wall_clock64();
+    for (uint32_t poll = 1;; ++poll) {
+        // relaxed polls (an acquire per poll would invalidate the L2 each time)
+        if (ld_agent(gen) != seen) return true;
+        if ((poll & 31u) == 0u) {
+            if (ld_agent(&ctl->stop) != 0u) return false;
+            const unsigned long long now = wall_clock64();
+            const bool late = now - run_start(ctl) > R.run_ticks;
+            if (late || now - t0 > R.spin_ticks) {
+                atomicOr(&ctl->error, late ? kErrTimeout : kErrStall);
+                atomicCAS(&ctl->stop, 0u, kStopError);
+                return false;
             }
         }
-        __threadfence(); // acquire the epilogue's writes and the other workgroups' round
-        sc = read_round_ctl(ctl, single);
+        // poll quickly at first (short rounds), then back off: long rounds would otherwise have every
+        // idle workgroup reading the barrier lines while the busy ones work
+        if (poll < 256u) __builtin_amdgcn_s_sleep(2);
+        else __builtin_amdgcn_s_sleep(32);
     }
-    ++gen;
+}
+
+// Grid barrier between rounds, two levels: a workgroup arrives at its group's
+// counter (kBarGroup workgroups); the last of a group arrives at the top
+// counter; the last group runs the epilogue and publishes the next round's
+// control words with the release of the top counter; each group's last
+// arrival, which waited there, copies them to its group's line and releases
+// the group.  `gen` is the number of barriers passed.  A workgroup that did
+// work in the round releases it first (agent scope); the caller acquires
+// before it touches lineage state again.  On return sc holds the next round's
+// control words (stop set if any wait gave up).
+__device__ __forceinline__ void grid_sync(Ctl *ctl, const RunArgs &R, uint32_t gen, bool worked, RoundCtl &sc) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (worked) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const uint32_t g = blockIdx.x / kBarGroup;
+        const uint32_t n_groups = (gridDim.x + kBarGroup - 1) / kBarGroup;
+        const uint32_t members = min(kBarGroup, gridDim.x - g * kBarGroup);
+        BarSlot &G = ctl->grp[g];
+        RoundCtl c{0u, 0u, 0u, kStopError};
+        if (atomicAdd(&G.arrived, 1u) == members - 1u) {
+            st_agent(&G.arrived, 0u);
+            if (atomicAdd(&ctl->top.arrived, 1u) == n_groups - 1u) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                st_agent(&ctl->top.arrived, 0u);
+                c = run_epilogue(ctl, R);
+                st_agent(&ctl->top.pub[0], c.r);
+                st_agent(&ctl->top.pub[1], c.n_main);
+                st_agent(&ctl->top.pub[2], c.n_solo);
+                st_agent(&ctl->top.pub[3], c.stop);
+                __hip_atomic_store(&ctl->top.gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else if (wait_gen(ctl, R, &ctl->top.gen, gen)) {
+                c = RoundCtl{ld_agent(&ctl->top.pub[0]), ld_agent(&ctl->top.pub[1]), ld_agent(&ctl->top.pub[2]),
+                             ld_agent(&ctl->top.pub[3])};
+            }
+            // release the group, also after giving up (its members then read the stop)
+            st_agent(&G.pub[0], c.r);
+            st_agent(&G.pub[1], c.n_main);
+            st_agent(&G.pub[2], c.n_solo);
+            st_agent(&G.pub[3], c.stop);
+            __hip_atomic_store(&G.gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (wait_gen(ctl, R, &G.gen, gen)) {
+            c = RoundCtl{ld_agent(&G.pub[0]), ld_agent(&G.pub[1]), ld_agent(&G.pub[2]), ld_agent(&G.pub[3])};
+        }
+        sc = c;
+    }
     __syncthreads();
 }
 
@@ -1684,33 +1755,41 @@ __global__ __launch_bounds__(256) void k_run(RoundArgs A, RunArgs R) {
     if (threadIdx.x == 0) {
         // the first workgroup to start sets the launch's start time (k_run_reset cleared it)
         atomicCAS(&A.ctl->t_start, 0ull, wall_clock64());
-        __threadfence();
         sc = read_round_ctl(A.ctl, kSingleJob);
     }
     __syncthreads();
     if (kLds) stage_table(A);
-    uint32_t gen = 0;
-    for (;;) {
+    unsigned long long philox = 0, draws = 0; // this lane's op counts over all rounds
+    for (uint32_t gen = 0;; ++gen) {
         const RoundCtl c = sc; // workgroup-uniform
         if (c.stop != 0u) break;
         const RoundPlan pl = plan_round<kSingleJob>(A, c.n_main, c.n_solo);
-        if (pl.mode != kPlanIdle) {
+        const bool work = pl.mode != kPlanIdle;
+        if (work) {
+            // acquire the previous rounds' lineage state (other workgroups' releases)
+            if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __syncthreads();
             Counters cnt;
             round_share<kSingleJob, kLds>(A, c.r, pl, c.n_main, c.n_solo, cnt, obuf);
-            flush_counters_block(A.ctl, cnt);
+            philox += cnt.philox;
+            draws += cnt.draws;
         }
-        grid_sync(A.ctl, R, gen, sc, kSingleJob);
+        grid_sync(A.ctl, R, gen, work, sc);
     }
+    flush_counters_block(A.ctl, philox, draws);
 }
 
 // Clears a persistent run's barrier and stop state before a launch (a resume
 // included: the run goes on from the round its control block holds).
 __global__ void k_run_reset(Ctl *ctl) {
-    ctl->bar_arrived = 0;
-    ctl->bar_gen = 0;
-    ctl->stop = 0;
-    ctl->first_round = ctl->round;
-    ctl->t_start = 0;
+    const uint32_t t = threadIdx.x;
+    if (t < kMaxBarGroups) ctl->grp[t] = BarSlot{};
+    if (t == 0) {
+        ctl->top = BarSlot{};
+        ctl->stop = 0;
+        ctl->first_round = ctl->round;
+        ctl->t_start = 0;
+    }
 }
 
 // Single-thread epilogue of a round: publish the survivor count to the
@@ -2882,7 +2961,11 @@ int persistent_grid(const PersistentLane &L, uint32_t variant, const nh_config &
     int per_cu = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, run_kernel(variant), (int)cfg.block_size, lds));
     per_cu = std::min<int>(per_cu, (int)cfg.blocks_per_cu);
+    while (per_cu > 1 && (uint64_t)per_cu * L.n_cu > (uint64_t)kBarGroup * kMaxBarGroups) --per_cu;
     if (per_cu < 1) return fail(NH_EINVAL, "no workgroup of %u threads fits a compute unit", cfg.block_size);
+    if ((uint64_t)per_cu * L.n_cu > (uint64_t)kBarGroup * kMaxBarGroups)
+        return fail(NH_EDEVICE, "%d compute units exceed the grid barrier's %u workgroups", L.n_cu,
+                    kBarGroup * kMaxBarGroups);
     grid = (uint32_t)(per_cu * L.n_cu);
     return NH_OK;
 }
@@ -2903,7 +2986,7 @@ int enqueue_persistent(PersistentLane &L, uint32_t variant, const RoundArgs &ra,
     std::lock_guard<std::mutex> lock(L.mu);
     HIP_TRY(hipEventRecord(L.in, stream));
     HIP_TRY(hipStreamWaitEvent(L.stream, L.in, 0));
-    k_run_reset<<<1, 1, 0, L.stream>>>(ra.ctl);
+    k_run_reset<<<1, kMaxBarGroups, 0, L.stream>>>(ra.ctl);
     if (t0) HIP_TRY(hipEventRecord(t0, L.stream));
     if (L.coop)
         HIP_TRY(hipLaunchCooperativeKernel(run_kernel(variant), dim3(grid), dim3(cfg.block_size), args,
@@ -3312,6 +3395,11 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
         HIP_TRY(hipEventElapsedTime(&x, ev_pool[2 * k], ev_pool[2 * k + 1]));
         round_ms += x;
     }
+    unsigned long long philox_calls = 0, exp_draws = 0;
+    for (uint32_t k = 0; k < kOpSlots; ++k) {
+        philox_calls += hctl.ops[k].philox;
+        exp_draws += hctl.ops[k].draws;
+    }
     if (stats) {
         for (uint32_t j = 0; j < n_jobs; ++j) {
             stats[j].events = hs[j].events;
@@ -3321,8 +3409,8 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
             stats[j].rounds = final_round;
             stats[j].richness = hs[j].rich_count;
             stats[j].device_ms = ms;
-            stats[j].philox_calls = hctl.philox_calls;
-            stats[j].exp_draws = hctl.exp_draws;
+            stats[j].philox_calls = philox_calls;
+            stats[j].exp_draws = exp_draws;
             stats[j].round_kernels = rounds_enqueued;
             stats[j].round_kernel_ms = round_ms;
         }
