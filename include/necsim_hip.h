@@ -349,6 +349,22 @@ int nh_simulate_device(const nh_scenario *scenario, uint64_t seed, const uint64_
 int nh_simulate_async(const nh_scenario *scenario, uint64_t seed, const uint64_t *d_sample_ids, uint64_t n,
                       uint64_t *d_species_out, uint64_t *d_richness_out, const nh_config *cfg, void *stream);
 
+/* nh_simulate_async for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same enqueue-only run, outputs and failure reporting, with no
+ * allocation at all.  The workspace is a 64 MiB device array inside the
+ * library (one per device, reserved when the library's code is loaded on that
+ * device and held until the process ends), which limits a run to the samples
+ * whose nh_workspace_bytes(n, 1) fits 64 MiB (about 480,000; NH_EINVAL beyond,
+ * with the limit in the message).  Every call on a device shares that array
+ * and overwrites what the last call left there (each call initialises what it
+ * reads), so calls on one device whose work can overlap (different streams
+ * with no ordering between them) race; calls on one stream are ordered.  The
+ * first call on a device looks the array's address up and creates the
+ * library's per-device stream and events; later calls only enqueue. */
+int nh_simulate_noalloc(const nh_scenario *scenario, uint64_t seed, const uint64_t *d_sample_ids, uint64_t n,
+                        uint64_t *d_species_out, uint64_t *d_richness_out, const nh_config *cfg, void *stream);
+
 /* One job with host buffers: uploads the samples, runs, downloads species
  * (n u64) and the richness.  Blocking; uses the default stream. */
 int nh_simulate(const nh_scenario *scenario, uint64_t seed, const uint64_t *h_sample_ids, uint64_t n,

@@ -133,6 +133,8 @@ _lib.nh_simulate_device.restype = C.c_int
 _lib.nh_simulate_async.argtypes = [C.c_void_p, C.c_uint64, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
                                    C.POINTER(nh_config), C.c_void_p]
 _lib.nh_simulate_async.restype = C.c_int
+_lib.nh_simulate_noalloc.argtypes = _lib.nh_simulate_async.argtypes
+_lib.nh_simulate_noalloc.restype = C.c_int
 _lib.nh_simulate.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64), C.c_uint64, C.POINTER(C.c_uint64),
                              C.POINTER(C.c_uint64), C.POINTER(nh_stats)]
 _lib.nh_simulate.restype = C.c_int
@@ -173,6 +175,7 @@ nh_event_stream = _lib.nh_event_stream
 nh_simulate_device = _lib.nh_simulate_device
 nh_simulate = _lib.nh_simulate
 nh_simulate_async = _lib.nh_simulate_async
+nh_simulate_noalloc = _lib.nh_simulate_noalloc
 nh_last_error = _lib.nh_last_error
 nh_version = _lib.nh_version
 nh_measure_mix_peak = _lib.nh_measure_mix_peak
@@ -189,7 +192,7 @@ nh_server_destroy = _lib.nh_server_destroy
 
 EXPORTED = ["nh_scenario_create", "nh_scenario_create_implicit", "nh_scenario_destroy", "nh_scenario_individuals", "nh_scenario_table_bytes",
             "nh_workspace_bytes", "nh_scenario_footprint_bytes", "nh_batch_run", "nh_batch_resume", "nh_event_stream",
-            "nh_simulate_device", "nh_simulate_async",
+            "nh_simulate_device", "nh_simulate_async", "nh_simulate_noalloc",
             "nh_simulate", "nh_last_error", "nh_version", "nh_server_bytes", "nh_server_create",
             "nh_server_submit", "nh_server_progress", "nh_server_poll", "nh_server_drain", "nh_server_destroy",
             "nh_measure_mix_peak", "nh_measure_gather", "nh_measure_event_latency", "nh_eval_primitives"]
@@ -310,6 +313,21 @@ def simulate_async(scenario: Scenario, seed: int, samples, out, rich=None, confi
                                   rich.data_ptr() if rich is not None else None,
                                   C.byref(config) if config is not None else None, C.c_void_p(s.cuda_stream)),
            "nh_simulate_async")
+
+
+def simulate_noalloc(scenario: Scenario, seed: int, samples, out, rich=None, config: nh_config | None = None,
+                     stream=None) -> None:
+    """nh_simulate_noalloc: as simulate_async, with the library's fixed device scratch as the
+    workspace (no allocation; at most about 480,000 samples)."""
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    n = samples.numel()
+    _check(_lib.nh_simulate_noalloc(scenario.handle, int(seed) & (2**64 - 1), samples.data_ptr() if n else None, n,
+                                    out.data_ptr() if out.numel() else None,
+                                    rich.data_ptr() if rich is not None else None,
+                                    C.byref(config) if config is not None else None, C.c_void_p(s.cuda_stream)),
+           "nh_simulate_noalloc")
 
 
 def workspace_bytes(n_total: int, n_jobs: int) -> int:

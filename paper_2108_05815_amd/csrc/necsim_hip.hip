@@ -2999,6 +2999,34 @@ int enqueue_persistent(PersistentLane &L, uint32_t variant, const RoundArgs &ra,
     return NH_OK;
 }
 
+// Workspace of nh_simulate_noalloc: a file-scope device array, one copy per
+// device that the library runs on, held until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): it looks the device address up once per device
+// and passes that.
+constexpr uint64_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of `scratch` on the current device (looked up at the first
+// call on that device, with the device current).
+int scratch_address(void *&out) {
+    static std::mutex mu;
+    static void *addr[64] = {};
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(NH_EDEVICE, "device %d is beyond the library's 64", dev);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(NH_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        addr[dev] = p;
+    }
+    out = addr[dev];
+    return NH_OK;
+}
+
 // Round-kernel arguments of a run in workspace ws laid out as L.
 RoundArgs round_args(char *ws, const Workspace &L, uint32_t n_jobs, uint64_t n_total, uint32_t grid,
                      const nh_config &cfg) {
@@ -3720,6 +3748,30 @@ NH_API int nh_simulate_async(const nh_scenario *scenario, uint64_t seed, const u
                                   stream);
     (void)hipFreeAsync(ws, stream);
     return rc;
+}
+
+NH_API int nh_simulate_noalloc(const nh_scenario *scenario, uint64_t seed, const uint64_t *d_sample_ids,
+                               uint64_t n, uint64_t *d_species_out, uint64_t *d_richness_out, const nh_config *cfg_in,
+                               void *stream_ptr) {
+    nh_config cfg;
+    fill_config(cfg_in, cfg);
+    if (int rc = check_single(scenario, d_sample_ids, n, d_species_out, cfg)) return rc;
+    if (nh_workspace_bytes(n, 1) > kScratchBytes) {
+        uint64_t lo = 0, hi = n; // the largest run the scratch holds
+        while (hi - lo > 1) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (nh_workspace_bytes(mid, 1) <= kScratchBytes) lo = mid;
+            else hi = mid;
+        }
+        return fail(NH_EINVAL, "nh_simulate_noalloc: %llu samples need %llu workspace bytes; its scratch holds %llu "
+                    "bytes, at most %llu samples", (unsigned long long)n,
+                    (unsigned long long)nh_workspace_bytes(n, 1), (unsigned long long)kScratchBytes,
+                    (unsigned long long)lo);
+    }
+    void *ws = nullptr;
+    if (int rc = scratch_address(ws)) return rc;
+    return enqueue_single(scenario, seed, d_sample_ids, n, d_species_out, d_richness_out, (char *)ws, cfg,
+                          (hipStream_t)stream_ptr);
 }
 
 NH_API int nh_simulate(const nh_scenario *scenario, uint64_t seed, const uint64_t *h_sample_ids, uint64_t n,
