@@ -61,8 +61,11 @@ SERVE_DEFAULTS = {"horizon_step_max": 64.0, "solo_max": 256, "solo_step": 512.0}
 
 
 def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, lineage_capacity: int | None = None,
-               max_jobs: int = 2048, lookahead: int = 64, config=None, workers: int = 4, timeout_s: float = 900.0):
-    """Serve the stream; returns latency percentiles, throughput and admission statistics."""
+               max_jobs: int = 2048, lookahead: int = 64, config=None, workers: int = 4, timeout_s: float = 900.0,
+               collect: bool = False):
+    """Serve the stream; returns latency percentiles, throughput and admission statistics.  collect:
+    also return each request's result as (richness, SHA-256 of its species array in sample order),
+    read back on completion (for parity checks; it adds a device-to-host copy per request)."""
     import torch
 
     if config is None:
@@ -79,6 +82,7 @@ def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, linea
     n = len(requests)
     lat = np.full(n, np.nan)
     per_request = {}  # request index -> (rounds, events, lineages) from its completion
+    results = {}      # request index -> (richness, species digest) when collecting
     events = individuals = 0
     building = {}
     nxt = done = 0
@@ -110,6 +114,10 @@ def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, linea
                     raise RuntimeError(f"request {idx} failed with status {c['status']}")
                 lat[idx] = t_done - arrivals[idx]
                 per_request[idx] = (int(c["rounds"]), int(c["events"]), int(c["lineages"]))
+                if collect:
+                    import hashlib
+                    species = c["held"][2].cpu().numpy().view(np.uint64)
+                    results[idx] = (int(c["richness"]), hashlib.sha256(species.astype("<u8").tobytes()).hexdigest())
                 events += c["events"]
                 individuals += c["lineages"]
                 done += 1
@@ -127,7 +135,7 @@ def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, linea
             "offered_requests_per_s": n / float(arrivals[-1] - arrivals[0]) if n > 1 else None,
             "lineage_capacity": int(lineage_capacity), "max_jobs": max_jobs,
             "peak_pending": int(peak_pending), "peak_active": int(peak_active),
-            "latency": _percentiles(lat), "latencies_s": lat, "per_request": per_request,
+            "latency": _percentiles(lat), "latencies_s": lat, "per_request": per_request, "results": results,
             # the stream is sustained if requests arriving late wait no longer than early ones
             "median_latency_first_third_ms": float(first * 1e3), "median_latency_last_third_ms": float(last * 1e3),
             "sustained": bool(last <= 2.0 * first + 0.05)}

@@ -1,12 +1,12 @@
 """GPU parity: species identities from the HIP library (through the C ABI)
 must equal the CPU oracle's bit for bit, on the same seeded inputs.
 
-Small and ragged cases are compared in full; the full-size workloads are
-compared in full where the culled oracle is fast (configs 1 and 2, and the
-256-scenario mix, whose oracle runs in a pool of host processes while the GPU
-works) and on uniformly sampled outputs traced one by one otherwise (config 3),
-together with properties that hold at any size (richness = distinct ids,
-duplicates agree, results independent of batching and tuning)."""
+Small and ragged cases are compared in full, and so are the full-size
+workloads: configs 1 and 2 directly, the 1024 x 1024 habitat (config 3) and the
+256-scenario mix (config 4) by a digest of each species array against the
+culled oracle run meanwhile in host processes (tests/oracle_pool.py), together
+with properties that hold at any size (richness = distinct ids, duplicates
+agree, results independent of batching, launch form and tuning)."""
 import os
 import sys
 import time
@@ -235,21 +235,64 @@ def test_repeat_runs_are_identical(B):
 # Config 3: 1024 x 1024 fractal habitat, per-deme tables, sampled outputs       #
 # --------------------------------------------------------------------------- #
 
-def test_config3_full_size_sampled(B):
-    wl = W.config3()
-    say("config 3: building per-deme tables")
-    t0 = time.time()
-    scn = B.Scenario.from_workload(wl)
-    say(f"config 3: tables {scn.table_bytes / 2**30:.2f} GiB in {time.time() - t0:.1f} s; simulating", len(wl.samples))
-    got, rich, st = B.simulate(scn, wl.seeds[0], wl.samples)
-    say("config 3:", st)
-    assert rich == len(np.unique(got))
-    assert st["speciated"] + st["merged"] == len(wl.samples)
-    osc = oracle.Scenario(wl.capacity, wl.weights, wl.nu, mode=1)
-    pick = np.random.default_rng(3).choice(len(wl.samples), size=10, replace=False)
-    say("config 3: oracle traces of", len(pick), "samples")
-    ref, _, ev = osc.simulate_naive(wl.seeds[0], wl.samples[pick])
-    assert np.array_equal(got[pick], ref), (got[pick], ref)
+def _start_pool(*args):
+    """The culled oracle of a whole configuration in a separate host process pool (tests/oracle_pool.py)."""
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    return subprocess.Popen([sys.executable, os.path.join(here, "oracle_pool.py"), *args],
+                            stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+
+
+def _pool_results(pool, timeout):
+    import json
+    try:
+        out, err = pool.communicate(timeout=timeout)
+    finally:
+        if pool.poll() is None:
+            pool.kill()
+            pool.wait()
+    assert pool.returncode == 0, err[-2000:]
+    return [json.loads(line) for line in out.splitlines() if line.startswith("{")]
+
+
+def _digest(a):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a).astype("<u8").tobytes()).hexdigest()
+
+
+def test_config3_full_parity(B):
+    """All 330,302 samples of the 1024 x 1024 habitat (per-deme tables, about 10 GiB) against the
+    culled oracle over the same samples, run meanwhile in a host process (about a minute, about
+    11 GB of lazily built per-deme tables), compared by the SHA-256 of the species array."""
+    pool = _start_pool("--config", "3", "--split", "1", "--workers", "1")
+    try:
+        wl = W.config3()
+        say("config 3: building per-deme tables")
+        t0 = time.time()
+        scn = B.Scenario.from_workload(wl)
+        say(f"config 3: tables {scn.table_bytes / 2**30:.2f} GiB in {time.time() - t0:.1f} s; simulating",
+            len(wl.samples))
+        got, rich, st = B.simulate(scn, wl.seeds[0], wl.samples)
+        say("config 3:", st)
+        assert rich == len(np.unique(got))
+        assert st["speciated"] + st["merged"] == len(wl.samples)
+        scn.close()
+        say("config 3: waiting for the oracle (all samples, culled)")
+        lines = _pool_results(pool, 900)
+    finally:
+        if pool.poll() is None:
+            pool.kill()
+            pool.wait()
+    ref = [d for d in lines if "sha256" in d]
+    say("config 3: oracle", [d for d in lines if "part" in d])
+    assert len(ref) == 1
+    if _digest(got) != ref[0]["sha256"]:  # name the first differing samples, traced one by one
+        osc = oracle.Scenario(wl.capacity, wl.weights, wl.nu, mode=1)
+        pick = np.random.default_rng(3).choice(len(wl.samples), size=20, replace=False)
+        exp, _, _ = osc.simulate_naive(wl.seeds[0], wl.samples[pick])
+        raise AssertionError(f"config 3 species differ from the oracle; sampled mismatches: "
+                             f"{np.flatnonzero(exp != got[pick]).tolist()}")
+    assert rich == ref[0]["richness"]
 
 
 # --------------------------------------------------------------------------- #
@@ -260,13 +303,8 @@ def test_config4_full_parity_and_alone_equals_mix(B, torch_mod):
     """All 256 scenarios of the mix (38.6 M samples) in one batch: every species id equals the
     culled oracle's (run meanwhile in a separate process pool on the host's cores, compared by a
     digest of each scenario's species array), and a few scenarios run alone equal the mix."""
-    import hashlib
-    import json
-    import subprocess
     torch = torch_mod
-    here = os.path.dirname(os.path.abspath(__file__))
-    pool = subprocess.Popen([sys.executable, os.path.join(here, "oracle_pool.py"), "--workers", "16"],
-                            stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+    pool = _start_pool("--config", "4", "--workers", "16")
     try:
         wls = W.config4()
         dev = torch.device("cuda:0")
@@ -288,17 +326,14 @@ def test_config4_full_parity_and_alone_equals_mix(B, torch_mod):
         for k in range(len(wls)):
             assert got_rich[k] == len(np.unique(got[k])) == stats[k]["richness"]
         say("config 4: waiting for the oracle pool")
-        out, err = pool.communicate(timeout=600)
+        lines = _pool_results(pool, 600)
     finally:
         if pool.poll() is None:
             pool.kill()
             pool.wait()
-    assert pool.returncode == 0, err[-2000:]
-    ref = {d["k"]: d for d in (json.loads(line) for line in out.splitlines() if line.startswith("{"))}
+    ref = {d["k"]: d for d in lines}
     assert sorted(ref) == list(range(len(wls)))
-    bad = [k for k in range(len(wls))
-           if hashlib.sha256(got[k].astype("<u8").tobytes()).hexdigest() != ref[k]["sha256"]
-           or got_rich[k] != ref[k]["richness"]]
+    bad = [k for k in range(len(wls)) if _digest(got[k]) != ref[k]["sha256"] or got_rich[k] != ref[k]["richness"]]
     if bad:  # name the first differing samples of the first bad scenario
         k = bad[0]
         osc = oracle.Scenario(wls[k].capacity, wls[k].weights, wls[k].nu, mode=wls[k].mode)

@@ -1,6 +1,10 @@
 """GPU tests of the continuous-batching engine (nh_server_*): jobs submitted while others
 run are admitted as lineage slots free up, and each result is bitwise the same as the
-job run alone (and as the oracle)."""
+job run alone (and as the oracle), on a hand-picked mix and on the served request
+stream of config 5 (every request against the culled oracle)."""
+import json
+import os
+import subprocess
 import sys
 
 import numpy as np
@@ -124,3 +128,37 @@ def test_server_isolates_bad_and_empty_jobs(env):
         too_big = torch.zeros(20_000, dtype=torch.int64, device=dev)
         srv.submit(9, scn, 5, too_big, torch.empty(20_000, dtype=torch.int64, device=dev))
     srv.close()
+
+
+def test_served_config5_stream_equals_the_oracle(env):
+    """The first 5 s of the config-5 request stream (Poisson 200 req/s; half config-4-like tori, half
+    non-spatial demes with J up to 10^6; nu down to 10^-6), served through the continuous-batching
+    server exactly as the benchmark serves it: every request's species array (by SHA-256) and
+    richness equal the culled oracle's, computed meanwhile in a host process pool."""
+    B, torch = env
+    from paper_2108_05815_amd import serve as S
+    here = os.path.dirname(os.path.abspath(__file__))
+    pool = subprocess.Popen([sys.executable, os.path.join(here, "oracle_pool.py"), "--config", "5",
+                             "--serve-seconds", "5", "--workers", "16"],
+                            stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+    try:
+        arrivals, specs = W.config5_requests(duration=5.0)
+        big_slow = [k for k, sp in enumerate(specs) if sp["kind"] == "nonspatial" and sp["J"] >= 1e5 and sp["nu"] <= 1e-5]
+        say(f"config 5: {len(specs)} requests, {len(big_slow)} non-spatial with J >= 1e5 and nu <= 1e-5")
+        assert big_slow, "the stream has no large slow non-spatial request"
+        free, _ = torch.cuda.mem_get_info()
+        served = S.run_served(arrivals, specs, hbm_budget_bytes=int(0.8 * free), collect=True)
+        say(f"config 5: served p50 {served['latency']['p50_ms']:.1f} ms, p99 {served['latency']['p99_ms']:.1f} ms")
+        say("config 5: waiting for the oracle pool")
+        out, err = pool.communicate(timeout=900)
+    finally:
+        if pool.poll() is None:
+            pool.kill()
+            pool.wait()
+    assert pool.returncode == 0, err[-2000:]
+    ref = {d["k"]: d for d in (json.loads(line) for line in out.splitlines() if line.startswith("{"))}
+    assert sorted(ref) == list(range(len(specs))) == sorted(served["results"])
+    bad = [k for k in range(len(specs))
+           if served["results"][k] != (ref[k]["richness"], ref[k]["sha256"])]
+    assert not bad, f"{len(bad)} served requests differ from the oracle, e.g. {[specs[k]['name'] for k in bad[:5]]}"
+    say("config 5: all", len(specs), "served requests equal the oracle")
