@@ -9,14 +9,17 @@ richness -- every kernel of the path, on inputs already resident in HBM.  The
 scenario tables are built once (they are the scenario, like model weights);
 each step uses its own seed.
 
-Before timing, the round kernels' performance knobs are autotuned on this
-workload (results never depend on them).  Prints one JSON line: lineage
-events/s (value), individuals/s, the round kernel's VALU roofline fraction (HIP
-events on the library's stream), the batched form (the 256-scenario mix in one
-run vs one scenario per run), the served form (a Poisson request stream through
-the continuous-batching server: p50/p99 latency and throughput, vs the same
-requests one per run), and the CPU oracle timed on a bounded sample of the
-plain workload.
+Before timing, the round kernels' performance knobs (launch form included) are
+autotuned on this workload (results never depend on them).  Prints one JSON
+line: lineage events/s (value), individuals/s, the round kernel's VALU roofline
+fraction (HIP events on the library's stream) and its serial bound, and beside
+them: the batched form (the 256-scenario mix in one run, knobs tuned on the mix,
+median of several runs, its own roofline, vs one scenario per run), the served
+form (a Poisson request stream through the continuous-batching server after a
+warm-up: p50/p99 latency, throughput, HBM budget, the slowest request against
+its run alone, vs the same requests one per run), the heterogeneous habitat
+(per-deme tables gathered from HBM), and the CPU oracle: single-threaded on a
+bounded sample of the plain workload and one process per host core on the mix.
 """
 from __future__ import annotations
 
@@ -48,15 +51,26 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the batched (C4) and served (C5) forms")
     ap.add_argument("--batch-plain-subset", type=int, default=32,
                     help="scenarios of the 256-scenario mix also run one per launch for the comparison")
-    ap.add_argument("--serve-seconds", type=float, default=5.0, help="length of the served request stream")
-    ap.add_argument("--serve-plain", type=int, default=48, help="requests of the stream also run one per launch")
-    ap.add_argument("--c3", action="store_true",
-                    help="also run the heterogeneous-habitat workload (1024x1024 fractal map, per-deme tables, "
-                         "10%% sample, nu = 1e-5) and report its gather traffic rate")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the served request stream")
+    ap.add_argument("--serve-warmup", type=float, default=5.0,
+                    help="served seconds before the measured stream (same rate, other requests; not measured)")
+    ap.add_argument("--serve-hbm-frac", type=float, default=0.8, help="serving budget as a fraction of free HBM")
+    ap.add_argument("--serve-plain", type=int, default=32, help="requests of the stream also run one per launch")
+    ap.add_argument("--batch-runs", type=int, default=5, help="timed runs of the batched form (median)")
+    ap.add_argument("--no-batch-tune", action="store_true", help="batched form on library defaults")
+    ap.add_argument("--cpu-c4-seconds", type=float, default=15.0,
+                    help="bound on the N-process oracle's wall time over the 256-scenario mix")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the heterogeneous-habitat workload (1024x1024 fractal map, per-deme tables, "
+                         "10%% sample, nu = 1e-5)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (calibrates rocprofv3 FETCH/WRITE_SIZE)")
     ap.add_argument("--event-stream", action="store_true",
                     help="only run the event-stream form on the 256x256 torus and print its JSON (for profiling)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the batched form (256-scenario mix) once per --batch-runs and print its JSON "
+                         "(for profiling; --batch-knobs fixes its knobs)")
+    ap.add_argument("--batch-knobs", default=None, help="JSON dict of knobs for the batched form instead of tuning")
     return ap.parse_args()
 
 
@@ -171,6 +185,65 @@ def latency_bound(B, scn, samples, out, ws, cfg, stream, run_ms: float) -> dict:
             "distinct_events": res["n_events"], "distinct_events_per_s": res["n_events"] / (run_ms * 1e-3)}
 
 
+def host_cpu() -> dict:
+    """The host's CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.lower().startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
+def _mix_worker(k):
+    import oracle
+    from paper_2108_05815_amd import workloads as W
+    w = W.config4()[k]
+    osc = oracle.Scenario(w.capacity, w.weights, w.nu, mode=w.mode)
+    _, ev, _ = osc.simulate_culled(w.seeds[0], w.samples, 2.0)
+    return k, len(w.samples), ev
+
+
+def cpu_baseline_mix(budget_s: float) -> dict:
+    """The culled oracle over the 256-scenario mix in one process per usable core (scenarios are
+    independent), smallest scenarios first, for a bounded wall time: the scenarios finished within
+    it give the rate."""
+    import multiprocessing as mp
+    from paper_2108_05815_amd import workloads as W
+    wls = W.config4()
+    order = sorted(range(len(wls)), key=lambda k: len(wls[k].samples))
+    n = host_cpu()["nproc"] or 1
+    done, lineages, events = 0, 0, 0
+    t0 = time.perf_counter()
+    el = 0.0
+    # fresh interpreters (this process holds the GPU; the workers never touch it)
+    with mp.get_context("spawn").Pool(processes=n) as pool:
+        it = pool.imap_unordered(_mix_worker, order, chunksize=1)
+        for _ in order:
+            try:
+                _, nl, ev = it.next(timeout=max(0.01, budget_s - (time.perf_counter() - t0)))
+            except mp.TimeoutError:
+                break
+            el = time.perf_counter() - t0
+            done, lineages, events = done + 1, lineages + nl, events + ev
+            if el >= budget_s:
+                break
+        pool.terminate()
+    return {"value": lineages / el if el > 0 else 0.0, "unit": "individuals/s", "cores": n, "kind": "oracle",
+            "events_per_s": events / el if el > 0 else 0.0, "individuals_per_s": lineages / el if el > 0 else 0.0,
+            **host_cpu(),
+            "sample": f"{done} of the 256 scenarios of the mix (smallest first, {lineages} lineages), culled "
+                      f"oracle (horizon step 2.0), one process per core on {n} cores, {el:.1f} s"}
+
+
 def cpu_baseline(wl, budget_s: float) -> dict:
     """The oracle's culled form on whole seeds of the same workload until the budget is spent."""
     import oracle
@@ -186,7 +259,7 @@ def cpu_baseline(wl, budget_s: float) -> dict:
         if el >= budget_s:
             break
     return {"value": events / el, "unit": "lineage events/s", "cores": 1, "kind": "oracle",
-            "individuals_per_s": runs * len(wl.samples) / el,
+            "individuals_per_s": runs * len(wl.samples) / el, **host_cpu(),
             "sample": f"{runs} whole seeds (42..{41 + runs}) of the same 65,536-lineage workload, "
                       f"single-threaded culled oracle (horizon step 1.0), {el:.1f} s"}
 
@@ -211,6 +284,9 @@ def main():
     from paper_2108_05815_amd import workloads as W
     if args.event_stream:
         print(json.dumps(stream_form(B, W, torch, torch.cuda.current_stream())), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps(batched_form(args, B, W, torch, compare=False)), flush=True)
         return
 
     wl = W.config2()
@@ -286,7 +362,10 @@ def main():
         "scenario_create_ms": create_ms,
         "roofline": {
             "bound": "alu",
-            "kernel": "k_round (horizon round: event sampling, dispersal, cull, compaction)",
+            "kernel": ("k_run (one persistent launch: every horizon round of the run, each event sampling, "
+                       "dispersal, cull and compaction, with a grid barrier between rounds)"
+                       if cfg.launch == B.NH_LAUNCH_PERSISTENT else
+                       "k_round (one horizon round: event sampling, dispersal, cull, compaction)"),
             "achieved": achieved,
             "peak": peak,
             "unit": "T lane-ops/s",
@@ -317,10 +396,16 @@ def main():
         line["event_stream"] = stream_form(B, W, torch, stream)
         line["batched"] = batched_form(args, B, W, torch)
         line["serve"] = served_form(args, W, torch)
-    if args.c3:
+    if not args.no_c3:
         line["c3"] = habitat_form(B, W, torch)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        if not args.no_extras:
+            line["cpu_baseline_c4"] = cpu_baseline_mix(args.cpu_c4_seconds)
+            b = line["batched"]
+            line["cpu_baseline_c4"]["gpu_batched_individuals_per_s"] = b["individuals_per_s"]
+            line["cpu_baseline_c4"]["gpu_over_cpu_individuals"] = (b["individuals_per_s"]
+                                                                   / line["cpu_baseline_c4"]["individuals_per_s"])
     print(json.dumps(line), flush=True)
 
 
@@ -418,8 +503,19 @@ def scn_table_sized(torch, dev, nbytes):
     return torch.empty(max(int(nbytes), 1 << 20), dtype=torch.uint8, device=dev)
 
 
-def batched_form(args, B, W, torch) -> dict:
-    """The 256-scenario mix in one batched run, against one scenario per run on a subset."""
+# the batched form stays one persistent launch per run; these are its tuned knobs
+BATCH_KNOBS = {"solo_max": [0, 64, 256], "horizon_step_max": [64.0, 256.0, 4096.0],
+               "horizon_growth": [1.25, 1.5, 2.0], "horizon0": [0.5, 2.0], "blocks_per_cu": [2, 4]}
+
+
+def batched_form(args, B, W, torch, compare: bool = True) -> dict:
+    """The 256-scenario mix in one batched run: knobs tuned on the mix itself (one run per
+    candidate), one warm-up run, then the median of args.batch_runs timed runs; the ALU roofline
+    of its round kernel and the serial bound of its slowest scenario; and the mix against one
+    scenario per run on a subset, compared in individuals/s (which no knob changes)."""
+    from paper_2108_05815_amd import autotune as AT
+    from paper_2108_05815_amd import roofline as RL
+    import statistics
     dev = torch.device("cuda:0")
     wls = W.config4()
     scns = [B.Scenario.from_workload(w) for w in wls]
@@ -428,47 +524,111 @@ def batched_form(args, B, W, torch) -> dict:
     n_total = sum(len(w.samples) for w in wls)
     ws = torch.empty(B.workspace_bytes(n_total, len(wls)), dtype=torch.uint8, device=dev)
     jobs = [(scns[k], wls[k].seeds[0], samples[k], outs[k], None) for k in range(len(wls))]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = B.batch_run(jobs, ws)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+
+    def timed(cfg):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = B.batch_run(jobs, ws, cfg)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, st
+
+    tuned = None
+    start = dict(AT.DEFAULT, launch=0, solo_max=0)
+    if args.batch_knobs:
+        tuned = dict(start, **json.loads(args.batch_knobs))
+    elif not args.no_batch_tune:
+        tuned, _, _ = AT.tune(lambda cfg: timed(cfg)[0], knobs=BATCH_KNOBS, start=start, reps=1)
+    knobs = tuned or start
+    cfg = AT.to_config(knobs, event_timing=1)
+    if compare:
+        timed(cfg)  # warm-up
+    runs = [timed(cfg) for _ in range(max(1, args.batch_runs))]
+    secs = [r[0] for r in runs]
+    el = statistics.median(secs)
+    st = runs[secs.index(el)][1] if el in secs else runs[0][1]
     ev = sum(x["events"] for x in st)
+    tot = st[0]
+    ops = RL.algorithmic_ops(tot["philox_calls"], tot["exp_draws"], ev)
+    round_s = tot["round_kernel_ms"] / 1e3
+    achieved = ops / round_s if round_s > 0 else 0.0
+    slow = max(range(len(wls)), key=lambda k: st[k]["rounds"])
+    roof = {"bound": "alu", "kernel": "k_run" if knobs.get("launch", 0) == 0 else "k_round",
+            "achieved": achieved / 1e12, "peak": RL.PEAK_LANE_OPS / 1e12, "unit": "T lane-ops/s",
+            "frac": achieved / RL.PEAK_LANE_OPS, "round_kernel_s": round_s, "launches": tot["round_kernels"],
+            "avg_launch_us": tot["round_kernel_ms"] * 1e3 / max(1, tot["round_kernels"]),
+            "ops_per_launch": ops / max(1, tot["round_kernels"])}
+    res = {"workload": "C4 mix: 256 scenarios, sides 64-512, capacity 1-4, sigma 1-6, nu 1e-6..1e-2",
+           "lineages": n_total, "tuned": knobs, "runs": len(secs), "seconds": el, "seconds_all": secs,
+           "events_per_s": ev / el, "individuals_per_s": n_total / el, "rounds": max(x["rounds"] for x in st),
+           "slowest_scenario": wls[slow].name, "roofline": roof}
+    if not compare:
+        return res
+    roof["latency"] = slowest_job_bound(B, torch, wls[slow], scns[slow], samples[slow], knobs)
     m = min(args.batch_plain_subset, len(wls))
     sub = jobs[:m]
     n_sub = sum(len(w.samples) for w in wls[:m])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st_b = B.batch_run(sub, ws)
+    B.batch_run(sub, ws, cfg)
     torch.cuda.synchronize()
     el_b = time.perf_counter() - t0
     t0 = time.perf_counter()
-    ev_p = 0
     for j in sub:
-        ev_p += B.batch_run([j], ws)[0]["events"]
+        B.batch_run([j], ws, cfg)
     torch.cuda.synchronize()
     el_p = time.perf_counter() - t0
-    ev_b = sum(x["events"] for x in st_b)
-    return {"workload": "C4 mix: 256 scenarios, sides 64-512, capacity 1-4, sigma 1-6, nu 1e-6..1e-2",
-            "lineages": n_total, "seconds": el, "events_per_s": ev / el, "individuals_per_s": n_total / el,
-            "rounds": st[0]["rounds"],
-            "subset": {"scenarios": m, "lineages": n_sub, "batched_s": el_b, "plain_s": el_p,
-                       "batched_events_per_s": ev_b / el_b, "plain_events_per_s": ev_p / el_p,
-                       "speedup": el_p / el_b}}
+    res["subset"] = {"scenarios": m, "lineages": n_sub, "batched_s": el_b, "plain_s": el_p,
+                     "batched_individuals_per_s": n_sub / el_b, "plain_individuals_per_s": n_sub / el_p,
+                     "speedup": el_p / el_b}
+    return res
+
+
+def slowest_job_bound(B, torch, wl, scn, samples, knobs) -> dict:
+    """Serial bound of the batch's slowest scenario (the job that finished last): its latest
+    speciation time t_max, from the speciation-event reporter of a run of that scenario alone,
+    times lambda is the expected number of events on the path that ends there (events come at
+    rate lambda); times the lone-lineage latency per event it is the time no schedule can beat."""
+    from paper_2108_05815_amd import autotune as AT
+    dev = torch.device("cuda:0")
+    n = len(wl.samples)
+    out = torch.empty(n, dtype=torch.int64, device=dev)
+    rep = {"spec_loc": torch.empty(n, dtype=torch.int32, device=dev),
+           "spec_time": torch.empty(n, dtype=torch.float64, device=dev)}
+    ws = torch.empty(B.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
+    cfg = AT.to_config(knobs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.batch_run([(scn, wl.seeds[0], samples, out, None, rep)], ws, cfg)
+    torch.cuda.synchronize()
+    alone_s = time.perf_counter() - t0
+    t_max = float(rep["spec_time"].max().item())
+    ns = B.measure_event_latency(scn, wl.seeds[0], 20000)
+    path = t_max * wl.lam
+    return {"scenario": wl.name, "lineages": n, "t_max": t_max, "path_events_estimate": path, "event_ns": ns,
+            "bound_s": path * ns * 1e-9, "alone_s": alone_s,
+            "what": "latest speciation time x lambda (expected events on that path) x lone-lineage latency"}
 
 
 def served_form(args, W, torch) -> dict:
-    """Poisson request stream (200 req/s) through the continuous-batching server, and its first
-    requests one per run for comparison."""
+    """Poisson request stream (200 req/s) through the continuous-batching server: args.serve_warmup
+    seconds of warm-up requests, then args.serve_seconds measured, all on one server whose budget
+    (lineage pool plus every live request's tables) is args.serve_hbm_frac of the free HBM; the
+    slowest measured request again alone on the idle device; and the first measured requests one
+    per run for comparison (individuals/s: no knob changes it)."""
     from paper_2108_05815_amd import binding as B
     from paper_2108_05815_amd import serve as S
-    arrivals, specs = W.config5_requests(duration=args.serve_seconds)
-    served = S.run_served(arrivals, specs, hbm_budget_bytes=64 << 30)
-    m = min(args.serve_plain, len(specs))
-    plain = S.run_plain(arrivals[:m], specs[:m])
-    prefix = served["latencies_s"][:m]
-    # the slowest request again, alone on the idle device: the floor its serial tail sets
-    slow = int(np.nanargmax(served["latencies_s"]))
+    total = args.serve_warmup + args.serve_seconds
+    arrivals, specs = W.config5_requests(duration=total)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(args.serve_hbm_frac * free)
+    served = S.run_served(arrivals, specs, hbm_budget_bytes=budget, measure_from=args.serve_warmup)
+    meas = served["measured"]
+    m = min(args.serve_plain, len(meas))
+    first = meas[:m]
+    plain = S.run_plain(arrivals[first], [specs[k] for k in first])
+    prefix = served["latencies_s"][first]
+    # the slowest measured request again, alone on the idle device: the floor its serial tail sets
+    slow = max(meas, key=lambda k: served["latencies_s"][k])
     wl, scn = S._build(specs[slow])
     n = scn.individuals
     dev = torch.device("cuda:0")
@@ -480,26 +640,30 @@ def served_form(args, W, torch) -> dict:
     st = B.batch_run([(scn, wl.seeds[0], s_ids, out_ids, None)], ws)[0]
     torch.cuda.synchronize()
     alone_s = time.perf_counter() - t0
-    rounds, events, _ = served["per_request"][slow]
-    out = {"workload": f"C5: Poisson 200 req/s for {args.serve_seconds:g} s, half spatial (C4-like), half "
-                       "non-spatial J 1e3..1e6, all individuals sampled",
-           "requests": served["requests"], "p50_ms": served["latency"]["p50_ms"],
-           "p99_ms": served["latency"]["p99_ms"], "max_ms": served["latency"]["max_ms"],
-           "events_per_s": served["events_per_s"], "individuals_per_s": served["individuals_per_s"],
-           "offered_requests_per_s": served["offered_requests_per_s"], "sustained": served["sustained"],
-           "median_latency_first_third_ms": served["median_latency_first_third_ms"],
-           "median_latency_last_third_ms": served["median_latency_last_third_ms"],
-           "lineage_capacity": served["lineage_capacity"],
-           "peak_pending": served["peak_pending"], "peak_active": served["peak_active"],
-           "plain_prefix": {"requests": m, "plain_p50_ms": plain["latency"]["p50_ms"],
-                            "plain_p99_ms": plain["latency"]["p99_ms"],
-                            "plain_events_per_s": plain["events_per_s"],
-                            "served_p50_ms": float(np.percentile(prefix, 50) * 1e3),
-                            "served_p99_ms": float(np.percentile(prefix, 99) * 1e3)},
-           "slowest_request": {"spec": {k: v for k, v in specs[slow].items() if k != "name"},
-                               "served_ms": float(served["latencies_s"][slow] * 1e3), "events": events,
-                               "alone_ms": alone_s * 1e3, "alone_events": st["events"]}}
-    return out
+    rounds, events, _, _ = served["per_request"][slow]
+    served_ms = float(served["latencies_s"][slow] * 1e3)
+    return {"workload": f"C5: Poisson 200 req/s, {args.serve_warmup:g} s warm-up then {args.serve_seconds:g} s "
+                        "measured, half spatial (C4-like), half non-spatial J 1e3..1e6, all individuals sampled",
+            "requests": served["requests"], "warmup_requests": served["warmup_requests"],
+            "p50_ms": served["latency"]["p50_ms"], "p99_ms": served["latency"]["p99_ms"],
+            "max_ms": served["latency"]["max_ms"], "mean_ms": served["latency"]["mean_ms"],
+            "events_per_s": served["events_per_s"], "individuals_per_s": served["individuals_per_s"],
+            "offered_requests_per_s": served["offered_requests_per_s"], "sustained": served["sustained"],
+            "median_latency_first_third_ms": served["median_latency_first_third_ms"],
+            "median_latency_last_third_ms": served["median_latency_last_third_ms"],
+            "peak_pending": served["peak_pending"], "peak_active": served["peak_active"],
+            "hbm": {"free_bytes": int(free), "budget_frac": args.serve_hbm_frac, "budget_bytes": budget,
+                    "lineage_pool_bytes": served["lineage_pool_bytes"], "lineage_capacity": served["lineage_capacity"],
+                    "table_budget_bytes": served["table_budget_bytes"],
+                    "table_peak_bytes": served["table_peak_bytes"]},
+            "plain_prefix": {"requests": m, "plain_p50_ms": plain["latency"]["p50_ms"],
+                             "plain_p99_ms": plain["latency"]["p99_ms"],
+                             "plain_individuals_per_s": plain["individuals_per_s"],
+                             "served_p50_ms": float(np.percentile(prefix, 50) * 1e3),
+                             "served_p99_ms": float(np.percentile(prefix, 99) * 1e3)},
+            "slowest_request": {"spec": {k: v for k, v in specs[slow].items() if k != "name"},
+                                "served_ms": served_ms, "events": events, "alone_ms": alone_s * 1e3,
+                                "alone_events": st["events"], "served_over_alone": served_ms / (alone_s * 1e3)}}
 
 
 if __name__ == "__main__":

@@ -156,7 +156,8 @@ typedef struct {
     uint64_t lineages;  /* samples simulated */
     uint64_t speciated; /* lineages that ended by speciating (representatives) */
     uint64_t merged;    /* lineages merged into an identical one by culling */
-    uint64_t rounds;    /* horizon rounds the job took part in */
+    uint64_t rounds;    /* horizon rounds the job took part in: to the round its last lineage retired in
+                           (for a suspended run, the rounds so far) */
     uint64_t richness;
     double device_ms;   /* stream time of the whole run (same for every job of a batch) */
     /* Totals of the whole run (the same for every job of a batch): */

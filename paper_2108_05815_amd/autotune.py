@@ -9,8 +9,12 @@ fastest on the workload at hand:
   round boundaries;
 * lanes per lineage: the queue length below which a lineage gets a group of
   8 lanes (its independent Philox blocks side by side) instead of one lane;
+* launch form: one persistent launch for the whole run (grid barrier between
+  rounds) or one launch per round replayed from captured graphs;
 * occupancy and launch shape: workgroups per CU, workgroup size, round kernels
   per captured graph;
+* solo tails (runs of several jobs): the live-lineage count below which a job
+  runs its lineages 8 lanes each on blocks of their own;
 * table placement: a shared dispersal table staged in LDS or read from global
   memory (L1/L2).
 
@@ -23,6 +27,8 @@ import statistics
 
 from . import binding as B
 
+# The launch form is a knob too ("launch": [0, 1], with "rounds_per_graph": [4, 8, 16] for the graph
+# form), searched only when asked for: the default search keeps one persistent launch per run.
 KNOBS = {
     "horizon0": [0.25, 0.5, 1.0, 2.0],
     "horizon_growth": [1.15, 1.25, 1.5, 2.0],
@@ -30,12 +36,11 @@ KNOBS = {
     "coop_divisor": [0, 32, 16, 8],   # coop_max = launch lanes / divisor + 1; 0 keeps one lane per lineage
     "blocks_per_cu": [2, 4, 8],
     "block_size": [128, 256],
-    "rounds_per_graph": [4, 8, 16],
     "table_placement": [0, 1],
 }
 
-DEFAULT = {"horizon0": 0.5, "horizon_growth": 1.25, "horizon_step_max": 4096.0, "coop_divisor": 16, "blocks_per_cu": 4, "block_size": 256,
-           "rounds_per_graph": 8, "table_placement": 0}
+DEFAULT = {"launch": 0, "horizon0": 0.5, "horizon_growth": 1.25, "horizon_step_max": 4096.0, "coop_divisor": 16,
+           "blocks_per_cu": 4, "block_size": 256, "rounds_per_graph": 8, "table_placement": 0}
 
 
 def n_compute_units() -> int:
@@ -51,7 +56,8 @@ def to_config(knobs: dict, n_cu: int | None = None, **extra) -> B.nh_config:
                          horizon_step_max=knobs.get("horizon_step_max", 4096.0),
                          blocks_per_cu=knobs["blocks_per_cu"], block_size=knobs["block_size"],
                          rounds_per_graph=knobs["rounds_per_graph"], table_placement=knobs["table_placement"],
-                         coop_max=(lanes // div + 1) if div else 1, **extra)
+                         coop_max=(lanes // div + 1) if div else 1, launch=knobs.get("launch", 0),
+                         solo_max=knobs.get("solo_max", 0), solo_step=knobs.get("solo_step", 0.0), **extra)
 
 
 def tune(run, knobs=None, start=None, reps: int = 3, passes: int = 1, log=None):

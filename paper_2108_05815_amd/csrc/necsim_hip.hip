@@ -3434,7 +3434,10 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
             stats[j].lineages = jobs[j].n;
             stats[j].speciated = hs[j].speciated;
             stats[j].merged = hs[j].merged;
-            stats[j].rounds = final_round;
+            // the job's own rounds: to the round it finished in (or the run's last round, if it has not)
+            stats[j].rounds = (hs[j].remaining == 0 && hs[j].done_round > hs[j].start_round)
+                                  ? hs[j].done_round - hs[j].start_round
+                                  : final_round;
             stats[j].richness = hs[j].rich_count;
             stats[j].device_ms = ms;
             stats[j].philox_calls = philox_calls;

@@ -60,22 +60,40 @@ def lineage_capacity_for_budget(budget_bytes: int, max_jobs: int) -> int:
 SERVE_DEFAULTS = {"horizon_step_max": 64.0, "solo_max": 256, "solo_step": 512.0}
 
 
+def table_bytes_estimate(spec: dict) -> int:
+    """Device bytes of a request's scenario tables before they are built: capacity (u32) and its
+    prefix (u64) per cell, and one 16-byte alias entry per kernel cell (shared table)."""
+    if spec["kind"] == "spatial":
+        cells = spec["L"] * spec["L"]
+        return 12 * cells + 8 + 16 * (2 * spec["R"] + 1) ** 2 + 4096
+    return 4096
+
+
 def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, lineage_capacity: int | None = None,
                max_jobs: int = 2048, lookahead: int = 64, config=None, workers: int = 4, timeout_s: float = 900.0,
-               collect: bool = False):
-    """Serve the stream; returns latency percentiles, throughput and admission statistics.  collect:
-    also return each request's result as (richness, SHA-256 of its species array in sample order),
-    read back on completion (for parity checks; it adds a device-to-host copy per request)."""
+               collect: bool = False, measure_from: float = 0.0, table_frac: float = 0.02):
+    """Serve the stream; returns latency percentiles, throughput and admission statistics.
+
+    HBM admission: the budget (default half of the free HBM) holds the resident lineage pool (the
+    server's workspace) and every live request's scenario tables.  table_frac of it is set aside for
+    tables; a request whose tables would not fit waits, unbuilt, until completed requests release
+    theirs, and a request is admitted into the running batch once its lineage slots are free.
+    measure_from: requests arriving before this time (s) warm the server up and are left out of
+    the latency and throughput figures.  collect: also return each request's result as (richness,
+    SHA-256 of its species array in sample order), read back on completion (for parity checks; it
+    adds a device-to-host copy per request)."""
     import torch
 
     if config is None:
         config = B.make_config(**SERVE_DEFAULTS)
     dev = torch.device("cuda:0")
+    if hbm_budget_bytes is None:
+        free, _ = torch.cuda.mem_get_info()
+        hbm_budget_bytes = int(0.5 * free)
+    table_budget = int(table_frac * hbm_budget_bytes)
     if lineage_capacity is None:
-        if hbm_budget_bytes is None:
-            free, _ = torch.cuda.mem_get_info()
-            hbm_budget_bytes = int(0.5 * free)
-        lineage_capacity = lineage_capacity_for_budget(hbm_budget_bytes, max_jobs)
+        lineage_capacity = lineage_capacity_for_budget(hbm_budget_bytes - table_budget, max_jobs)
+    pool_bytes = B.server_bytes(lineage_capacity, max_jobs)
     stream = torch.cuda.Stream()
     srv = B.Server(lineage_capacity, max_jobs=max_jobs, lookahead=lookahead, config=config, stream=stream)
     pool = cf.ThreadPoolExecutor(max_workers=workers)
@@ -83,8 +101,10 @@ def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, linea
     lat = np.full(n, np.nan)
     per_request = {}  # request index -> (rounds, events, lineages) from its completion
     results = {}      # request index -> (richness, species digest) when collecting
-    events = individuals = 0
+    tables = {}       # request index -> device bytes of its tables (reserved estimate, then actual)
+    table_live = table_peak = 0
     building = {}
+    waiting = []      # arrived requests whose tables do not fit yet, in arrival order
     nxt = done = 0
     peak_pending = peak_active = 0
     t0 = time.perf_counter()
@@ -94,10 +114,22 @@ def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, linea
             if now > timeout_s:
                 raise TimeoutError(f"serving stream did not finish in {timeout_s} s ({done}/{n} done)")
             while nxt < n and arrivals[nxt] <= now:
-                building[nxt] = pool.submit(_build, requests[nxt])
+                waiting.append(nxt)
                 nxt += 1
+            while waiting:
+                idx = waiting[0]
+                need = table_bytes_estimate(requests[idx])
+                if table_live + need > table_budget and table_live > 0:
+                    break
+                waiting.pop(0)
+                tables[idx] = need
+                table_live += need
+                building[idx] = pool.submit(_build, requests[idx])
             for idx in [k for k, f in building.items() if f.done()]:
                 wl, scn = building.pop(idx).result()
+                table_live += scn.table_bytes - tables[idx]
+                tables[idx] = scn.table_bytes
+                table_peak = max(table_peak, table_live)
                 with torch.cuda.stream(stream):
                     N = scn.individuals
                     samples = torch.arange(N, dtype=torch.int64, device=dev)
@@ -105,7 +137,7 @@ def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, linea
                     rich = torch.empty(1, dtype=torch.int64, device=dev)
                 srv.submit(idx, scn, wl.seeds[0], samples, out, rich)
             active, pending = srv.progress()
-            peak_pending = max(peak_pending, pending + len(building))
+            peak_pending = max(peak_pending, pending + len(building) + len(waiting))
             peak_active = max(peak_active, active)
             for c in srv.poll():
                 t_done = time.perf_counter() - t0
@@ -113,29 +145,38 @@ def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, linea
                 if c["status"] != 0:
                     raise RuntimeError(f"request {idx} failed with status {c['status']}")
                 lat[idx] = t_done - arrivals[idx]
-                per_request[idx] = (int(c["rounds"]), int(c["events"]), int(c["lineages"]))
+                per_request[idx] = (int(c["rounds"]), int(c["events"]), int(c["lineages"]), float(t_done))
                 if collect:
                     import hashlib
                     species = c["held"][2].cpu().numpy().view(np.uint64)
                     results[idx] = (int(c["richness"]), hashlib.sha256(species.astype("<u8").tobytes()).hexdigest())
-                events += c["events"]
-                individuals += c["lineages"]
+                c["held"][0].close()  # the request's tables go back to the budget
+                table_live -= tables.pop(idx)
                 done += 1
-            if not building and nxt < n and srv.progress()[0] == 0:
+            if not building and not waiting and nxt < n and srv.progress()[0] == 0:
                 time.sleep(min(0.0005, max(0.0, arrivals[nxt] - (time.perf_counter() - t0))))
         wall = time.perf_counter() - t0
     finally:
         pool.shutdown(wait=True)
         srv.close()
-    span = wall - float(arrivals[0]) if n else wall
-    third = max(1, n // 3)
-    first, last = np.median(lat[:third]), np.median(lat[-third:])
-    return {"requests": n, "wall_s": wall, "events": int(events), "individuals": int(individuals),
-            "events_per_s": events / span, "individuals_per_s": individuals / span,
-            "offered_requests_per_s": n / float(arrivals[-1] - arrivals[0]) if n > 1 else None,
+    meas = [k for k in range(n) if arrivals[k] >= measure_from]
+    m_lat = lat[meas]
+    events = sum(per_request[k][1] for k in meas)
+    individuals = sum(per_request[k][2] for k in meas)
+    # throughput of the measured requests: from the first measured arrival to the last measured completion
+    span = (max(per_request[k][3] for k in meas) - float(arrivals[meas[0]])) if meas else wall
+    third = max(1, len(meas) // 3)
+    first, last = (np.median(m_lat[:third]), np.median(m_lat[-third:])) if meas else (np.nan, np.nan)
+    return {"requests": len(meas), "warmup_requests": n - len(meas), "wall_s": wall, "events": int(events),
+            "individuals": int(individuals), "events_per_s": events / span, "individuals_per_s": individuals / span,
+            "offered_requests_per_s": (len(meas) / float(arrivals[meas[-1]] - arrivals[meas[0]])
+                                       if len(meas) > 1 else None),
+            "hbm_budget_bytes": int(hbm_budget_bytes), "lineage_pool_bytes": int(pool_bytes),
+            "table_budget_bytes": table_budget, "table_peak_bytes": int(table_peak),
             "lineage_capacity": int(lineage_capacity), "max_jobs": max_jobs,
             "peak_pending": int(peak_pending), "peak_active": int(peak_active),
-            "latency": _percentiles(lat), "latencies_s": lat, "per_request": per_request, "results": results,
+            "latency": _percentiles(m_lat), "latencies_s": lat, "measured": meas, "per_request": per_request,
+            "results": results,
             # the stream is sustained if requests arriving late wait no longer than early ones
             "median_latency_first_third_ms": float(first * 1e3), "median_latency_last_third_ms": float(last * 1e3),
             "sustained": bool(last <= 2.0 * first + 0.05)}

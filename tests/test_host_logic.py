@@ -16,7 +16,7 @@ def test_autotune_coordinate_descent_finds_separable_minimum(monkeypatch):
     from paper_2108_05815_amd import autotune as AT
     monkeypatch.setattr(AT, "n_compute_units", lambda: 256)
     target = {"horizon0": 1.0, "horizon_growth": 1.5, "horizon_step_max": 256.0, "coop_divisor": 8,
-              "blocks_per_cu": 2, "block_size": 128, "rounds_per_graph": 16, "table_placement": 1}
+              "blocks_per_cu": 2, "block_size": 128, "rounds_per_graph": 8, "table_placement": 1}
     seen = []
 
     def run(cfg):
@@ -36,6 +36,10 @@ def test_autotune_coordinate_descent_finds_separable_minimum(monkeypatch):
     for k in target:
         assert best[k] == target[k], k
     assert len(trials) == 1 + sum(len(v) - 1 for v in AT.KNOBS.values())
+    # the launch form is searched when asked for
+    knobs = dict(AT.KNOBS, launch=[0, 1])
+    best, t, _ = AT.tune(lambda cfg: float(cfg.launch != 1), knobs=knobs, reps=1)
+    assert best["launch"] == 1 and t == 0.0
 
 
 def test_autotune_config_mapping(monkeypatch):
