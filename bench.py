@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="bound on the oracle baseline's CPU time")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_round_c2_traffic.txt"),
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_run_c2_traffic.txt"),
                     help="HBM bytes per round launch from rocprofv3 FETCH_SIZE/WRITE_SIZE runs")
     ap.add_argument("--no-tune", action="store_true", help="use the library defaults instead of autotuning")
     ap.add_argument("--knobs", default=None, help="JSON dict of tuned knobs to use instead of autotuning")
@@ -71,6 +71,10 @@ def parse():
                     help="only run the batched form (256-scenario mix) once per --batch-runs and print its JSON "
                          "(for profiling; --batch-knobs fixes its knobs)")
     ap.add_argument("--batch-knobs", default=None, help="JSON dict of knobs for the batched form instead of tuning")
+    ap.add_argument("--profile-summary", default=None, metavar="DB",
+                    help="only summarise a rocprofv3 results database (no GPU): per-kernel trace statistics, and "
+                         "per-dispatch counter sums of the kernels matching --profile-kernel")
+    ap.add_argument("--profile-kernel", default="k_run|k_round", help="kernel-name regex for --profile-summary")
     return ap.parse_args()
 
 
@@ -264,8 +268,45 @@ def cpu_baseline(wl, budget_s: float) -> dict:
                       f"single-threaded culled oracle (horizon step 1.0), {el:.1f} s"}
 
 
+def profile_summary(db: str, kernel_re: str) -> dict:
+    """Kernel-trace statistics (per kernel name: calls, average/total/min/max duration) and counter
+    sums per dispatch (rocprofv3 reports counters per shader engine; they are added up) from a
+    rocprofv3 SQLite results database."""
+    import re
+    import sqlite3
+    con = sqlite3.connect(db)
+    tables = {r[0] for r in con.execute("select name from sqlite_master where type in ('table', 'view')")}
+
+    def short(name):
+        n = re.sub(r"\(anonymous namespace\)::", "", name)
+        if "rocprim" in n:
+            return "rocprim sort/scan kernels (all)"
+        return re.sub(r"\(.*$", "", n).replace("void ", "")
+
+    out = {"database": os.path.basename(db)}
+    if "kernels" in tables:
+        agg = {}
+        for name, dur in con.execute("select name, duration from kernels"):
+            agg.setdefault(short(name), []).append(dur / 1e3)
+        out["trace"] = [{"kernel": k, "calls": len(v), "avg_us": sum(v) / len(v), "total_ms": sum(v) / 1e3,
+                         "min_us": min(v), "max_us": max(v)}
+                        for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))]
+    if "counters_collection" in tables:
+        per = {}
+        for d, kname, c, v in con.execute("select dispatch_id, kernel_name, counter_name, sum(value) from "
+                                          "counters_collection group by dispatch_id, counter_name "
+                                          "order by dispatch_id"):
+            if re.search(kernel_re, kname):
+                per.setdefault(int(d), {"kernel": short(kname)})[c] = float(v)
+        out["counters"] = per
+    return out
+
+
 def main():
     args = parse()
+    if args.profile_summary:
+        print(json.dumps(profile_summary(args.profile_summary, args.profile_kernel)))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method shards by samples with no "
               "communication, and this benchmark measures a single GPU.", file=sys.stderr)
