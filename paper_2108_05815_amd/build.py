@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "necsim_hip.hip")
-# hipCUB sort and scan instantiations for the event stream (own translation unit)
+# radix sort and scan kernels of the event stream (own translation unit)
 SORT_SRC = os.path.join(HERE, "csrc", "stream_sort.hip")
 HEADER = os.path.join(ROOT, "include", "necsim_hip.h")
 LIB = os.path.join(HERE, "libnecsim_hip.so")

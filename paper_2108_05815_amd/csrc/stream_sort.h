@@ -1,7 +1,8 @@
-// Device-wide sort and scan primitives used by the event stream, instantiated
-// from hipCUB in their own translation unit.  Each call with tmp == nullptr
+// Device-wide sort and scan primitives used by the event stream (own kernels
+// for gfx950, in their own translation unit).  Each call with tmp == nullptr
 // only stores the scratch size it needs in tmp_bytes; otherwise tmp must hold
-// that many bytes.  All work is queued on `stream`.
+// that many bytes (hipErrorInvalidValue if it does not).  All work is queued on
+// `stream`.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstddef>
