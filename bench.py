@@ -78,6 +78,11 @@ def parse():
     return ap.parse_args()
 
 
+def note(*a):
+    """A progress line on stderr (the JSON line alone goes to stdout)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def traffic_from_profile(path: str) -> float | None:
     """HBM bytes per round launch recorded from rocprofv3 FETCH_SIZE and WRITE_SIZE runs, or None when
     the kernel source has changed since they were taken."""
@@ -353,11 +358,13 @@ def main():
             st = B.batch_run([(scn, 7, samples, out, rich)], ws, cfg, stream)[0]
             return st["device_ms"] / 1e3
 
+        note("autotuning the plain form")
         tuned, tuned_s, _ = AT.tune(one, reps=2)
         cfg = AT.to_config(tuned, event_timing=1)
     else:
         cfg = B.make_config(event_timing=1)
 
+    note("plain form (256x256 torus): warm-up and timed steps")
     for k in range(args.warmup):
         B.batch_run([(scn, 1000 + k, samples, out, rich)], ws, cfg, stream)
     torch.cuda.synchronize()
@@ -433,15 +440,21 @@ def main():
         host_s = time.perf_counter() - t0
         line["host_buffers"] = {"entry": "nh_simulate", "runs": 5, "ms_per_run": host_s * 200.0,
                                 "events_per_s": host_ev / host_s}
+        note("Poisson-count sampler")
         line["poisson_sampler"] = sampler_form(B, W, torch, cfg, stream)
+        note("event stream")
         line["event_stream"] = stream_form(B, W, torch, stream)
+        note("batched form (256-scenario mix): tuning, warm-up, timed runs")
         line["batched"] = batched_form(args, B, W, torch)
         line["serve"] = served_form(args, W, torch)
     if not args.no_c3:
+        note("heterogeneous habitat (1024x1024)")
         line["c3"] = habitat_form(B, W, torch)
     if not args.no_cpu:
+        note("CPU oracle, one thread")
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
         if not args.no_extras:
+            note("CPU oracle, one process per core, on the mix")
             line["cpu_baseline_c4"] = cpu_baseline_mix(args.cpu_c4_seconds)
             b = line["batched"]
             line["cpu_baseline_c4"]["gpu_batched_individuals_per_s"] = b["individuals_per_s"]
@@ -662,7 +675,9 @@ def served_form(args, W, torch) -> dict:
     arrivals, specs = W.config5_requests(duration=total)
     free, _ = torch.cuda.mem_get_info()
     budget = int(args.serve_hbm_frac * free)
-    served = S.run_served(arrivals, specs, hbm_budget_bytes=budget, measure_from=args.serve_warmup)
+    note(f"served form: {len(specs)} requests over {total:g} s")
+    served = S.run_served(arrivals, specs, hbm_budget_bytes=budget, measure_from=args.serve_warmup, progress_s=10.0)
+    note("served form: the first measured requests one per run")
     meas = served["measured"]
     m = min(args.serve_plain, len(meas))
     first = meas[:m]

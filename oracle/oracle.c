@@ -423,13 +423,17 @@ static uint64_t interval_draw(uint64_t seed, uint32_t loc, uint64_t k, uint32_t 
 /* 1 .. N place the points at k dt + U(r) dt.  The next event after t_last  */
 /* is the smallest point beyond it; an interval without one moves the        */
 /* search to interval k+1.  Needs mu <= 700 so that exp(-mu) is normal.      */
+/* The count itself: inversion of the Poisson cdf by sequential search         */
+/* (Devroye 1986, Non-Uniform Random Variate Generation, ch. X.3): the       */
+/* smallest n with u <= F(n) = sum_{j<=n} p_j, each term from the one before  */
+/* by one binary64 division and one product, the sum left to right.          */
 static uint32_t poisson_count(const or_scenario *s, double u) {
-    double p = s->p0, cdf = p;
-    uint32_t n = 0;
-    while (u > cdf && p > 0.0) {
-        n = n + 1;
-        p = p * (s->mu / (double)n);
-        cdf = cdf + p;
+    uint32_t n;
+    double term = s->p0, cdf = s->p0;
+    for (n = 0; u > cdf && term > 0.0;) {
+        ++n;
+        term *= s->mu / (double)n;
+        cdf += term;
     }
     return n;
 }

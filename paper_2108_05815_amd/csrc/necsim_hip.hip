@@ -375,13 +375,15 @@ __device__ __forceinline__ double next_event_time_wide(const JobView &v, uint32_
 // without one moves the search to interval k+1.
 __device__ __forceinline__ double u53(uint64_t r) { return (double)(r >> 11) * 0x1.0p-53; }
 
+// Inversion of the Poisson cdf by sequential search (Devroye 1986, Non-Uniform
+// Random Variate Generation, ch. X.3): the smallest n with u <= F(n).
 __device__ __forceinline__ uint32_t poisson_count(const JobView &v, double u) {
-    double p = v.p0, cdf = p;
-    uint32_t n = 0;
-    while (u > cdf && p > 0.0) {
-        n = n + 1;
-        p = p * (v.mu / (double)n);
-        cdf = cdf + p;
+    uint32_t n;
+    double term = v.p0, cdf = v.p0;
+    for (n = 0; u > cdf && term > 0.0;) {
+        ++n;
+        term *= v.mu / (double)n; // one division, one product, as the definition orders them
+        cdf += term;
     }
     return n;
 }

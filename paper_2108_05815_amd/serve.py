@@ -16,6 +16,7 @@ when it has arrived and the previous one has finished.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import sys
 import time
 
 import numpy as np
@@ -71,13 +72,15 @@ def table_bytes_estimate(spec: dict) -> int:
 
 def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, lineage_capacity: int | None = None,
                max_jobs: int = 2048, lookahead: int = 64, config=None, workers: int = 4, timeout_s: float = 900.0,
-               collect: bool = False, measure_from: float = 0.0, table_frac: float = 0.02):
+               collect: bool = False, measure_from: float = 0.0, table_frac: float = 0.02,
+               progress_s: float = 0.0):
     """Serve the stream; returns latency percentiles, throughput and admission statistics.
 
     HBM admission: the budget (default half of the free HBM) holds the resident lineage pool (the
     server's workspace) and every live request's scenario tables.  table_frac of it is set aside for
     tables; a request whose tables would not fit waits, unbuilt, until completed requests release
     theirs, and a request is admitted into the running batch once its lineage slots are free.
+    progress_s > 0: a line on stderr that often (requests done, active, waiting).
     measure_from: requests arriving before this time (s) warm the server up and are left out of
     the latency and throughput figures.  collect: also return each request's result as (richness,
     SHA-256 of its species array in sample order), read back on completion (for parity checks; it
@@ -108,9 +111,14 @@ def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, linea
     nxt = done = 0
     peak_pending = peak_active = 0
     t0 = time.perf_counter()
+    next_note = progress_s
     try:
         while done < n:
             now = time.perf_counter() - t0
+            if progress_s > 0 and now >= next_note:
+                print(f"[serve] {now:.0f} s: {done}/{n} done, {nxt} arrived, {len(waiting) + len(building)} waiting",
+                      file=sys.stderr, flush=True)
+                next_note += progress_s
             if now > timeout_s:
                 raise TimeoutError(f"serving stream did not finish in {timeout_s} s ({done}/{n} done)")
             while nxt < n and arrivals[nxt] <= now:
