@@ -87,7 +87,7 @@ class nh_primitive_io(C.Structure):
 
 class nh_server_config(C.Structure):
     _fields_ = [("lineage_capacity", C.c_uint64), ("max_jobs", C.c_uint32), ("lookahead", C.c_uint32),
-                ("cfg", nh_config)]
+                ("cfg", nh_config), ("tail_blocks", C.c_uint32)]
 
 
 class nh_completion(C.Structure):
@@ -365,11 +365,12 @@ class Server:
     while others run.  Keeps each job's tensors and scenario alive until its completion is polled."""
 
     def __init__(self, lineage_capacity: int, max_jobs: int = 1024, lookahead: int = 16,
-                 config: nh_config | None = None, stream=None):
+                 config: nh_config | None = None, stream=None, tail_blocks: int = 0):
         cfg = nh_server_config()
         cfg.lineage_capacity = lineage_capacity
         cfg.max_jobs = max_jobs
         cfg.lookahead = lookahead
+        cfg.tail_blocks = tail_blocks
         if config is not None:
             cfg.cfg = config
         h = C.c_void_p()

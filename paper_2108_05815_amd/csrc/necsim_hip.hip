@@ -213,6 +213,7 @@ struct JobView {
     uint64_t mig_thresh;
     uint32_t cap_local, cap_meta; // spatially implicit: the two communities' sizes
     double tau_t;                 // protracted speciation threshold time
+    uint32_t lds_base;            // first entry of the table's LDS copy (kLds forms)
 };
 
 // Op counters of one lane (summed per wave at the end of a kernel).
@@ -244,6 +245,7 @@ __device__ __forceinline__ JobView load_view(const JobDev *__restrict__ J) {
     v.p0 = J->p0;
     v.mig_thresh = J->mig_thresh;
     v.tau_t = J->tau_t;
+    v.lds_base = 0;
     if (J->mode == kModeImplicit) {
         v.cap_local = J->cap[0];
         v.cap_meta = J->cap[1];
@@ -526,10 +528,30 @@ __device__ __forceinline__ uint64_t species_of(const JobView &v, uint32_t loc, d
 // also read by the spatially implicit scenario, whose dispersal ignores it),
 // and a scheduling barrier keeps them ahead of the hash, whose first use of
 // them comes after it.
-template <bool kLds>
+// kUni: the wave works on one lineage (every active lane holds the same
+// values), so the table is read through the scalar data cache: the first
+// active lane's address, read as constant memory (tables never change while
+// kernels run).
+typedef const __attribute__((address_space(4))) uint32_t *ConstU32;
+
+__device__ __forceinline__ ConstU32 uniform_ptr(const void *p) {
+    const uint64_t b = (uint64_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return (ConstU32)(((uint64_t)hi << 32) | lo);
+}
+
+template <bool kLds, bool kUni = false>
 __device__ __forceinline__ uint2 table_row(const JobView &v, const Pos &p) {
-    if (kLds) return make_uint2(0u, v.n_shared);
+    if (kLds) return make_uint2(v.lds_base, v.lds_base + v.n_shared);
     const uint32_t cell = v.mode == NH_DISPERSAL_PER_DEME ? p.y * v.W + p.x : 0u;
+    if (kUni) {
+        const ConstU32 rp = uniform_ptr(v.row_ptr);
+        const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane(cell);
+        const uint2 row = make_uint2(rp[c], rp[c + 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        return row;
+    }
     const uint2 row = make_uint2(v.row_ptr[cell], v.row_ptr[cell + 1]);
     __builtin_amdgcn_sched_barrier(0);
     return row;
@@ -539,7 +561,7 @@ __device__ __forceinline__ uint2 table_row(const JobView &v, const Pos &p) {
 // from r2, the torus offset of the chosen entry, and the deme index from r3;
 // row is table_row of the lineage's cell (first and one-past-last entry).  A
 // table staged in LDS is always the shared one.
-template <bool kLds>
+template <bool kLds, bool kUni = false>
 __device__ __forceinline__ void disperse(const JobView &v, Pos &p, uint64_t r1, uint64_t r2, uint64_t r3,
                                          uint2 row) {
     if (!kLds && v.mode == kModeImplicit) {
@@ -554,7 +576,14 @@ __device__ __forceinline__ void disperse(const JobView &v, Pos &p, uint64_t r1, 
     }
     const uint32_t first = row.x, n = row.y - row.x;
     const uint32_t col = mulhi_index(r1, n);
-    const uint4 ent = kLds ? nh_lds_table[first + col] : v.table[first + col];
+    uint4 ent;
+    if (kUni) {
+        const ConstU32 tp = uniform_ptr(v.table);
+        const uint32_t e = 4u * (uint32_t)__builtin_amdgcn_readfirstlane(first + col);
+        ent = make_uint4(tp[e], tp[e + 1], tp[e + 2], tp[e + 3]);
+    } else {
+        ent = kLds ? nh_lds_table[first + col] : v.table[first + col];
+    }
     const uint64_t thresh = ((uint64_t)ent.y << 32) | ent.x;
     const bool primary = (r2 >> 11) < thresh;
     const uint32_t off = primary ? (ent.z & 0xFFFFu) : (ent.z >> 16);
@@ -875,7 +904,7 @@ __device__ __forceinline__ uint32_t group_sum8(uint32_t x) {
 // row is table_row of p on entry and of the moved p on return: the next
 // event's row pointers are requested as soon as the dispersal is known, so
 // their loads overlap the search and the next event's hash.
-template <bool kLds>
+template <bool kLds, bool kUni = false>
 __device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double &t, uint2 &row, uint32_t gl,
                                                uint32_t grp_base, Counters &cnt) {
     const uint64_t tb = (uint64_t)__double_as_longlong(t);
@@ -889,8 +918,8 @@ __device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double 
     const uint64_t r3 = ((uint64_t)from_odd(a3) << 32) | from_odd(a2);
     const bool spec = (r0 >> 11) < speciation_threshold<kLds>(v, p, t);
     Pos q = p;
-    disperse<kLds>(v, q, r1, r2, r3, row);
-    row = table_row<kLds>(v, q);
+    disperse<kLds, kUni>(v, q, r1, r2, r3, row);
+    row = table_row<kLds, kUni>(v, q);
 
     const double kf = floor(t * v.inv_dt);
     const bool wide = !(kf < 2147483648.0);
@@ -1036,6 +1065,35 @@ __device__ __forceinline__ uint32_t job_of(const JobDev *jobs, uint32_t n_jobs, 
     return lo;
 }
 
+// Relaxed agent-scope accesses to control words that other workgroups write.
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t *p, uint32_t x) {
+    __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Tail lane (servers): a job whose last lineage is all that is left of it
+// needs no more rounds, since a lone lineage has nothing to merge with.  The
+// round kernel hands such a lineage to this queue and a separate kernel
+// (k_tail, on compute units of its own) walks it to its speciation without
+// waiting for anyone's rounds.  Entry i sits in slot i % kTailCap: seq holds
+// i + 1 once it is filled and i + 1 | kTailCopied once a tail wave has read
+// it, which frees the slot for entry i + kTailCap.
+constexpr uint32_t kTailCap = 1024;
+constexpr uint32_t kTailCopied = 0x80000000u;
+struct TailQ {
+    uint32_t push;   // entries filled (reserved by a CAS that checks the slot is free)
+    uint32_t take;   // entries claimed by tail waves (only ready entries are claimed)
+    uint32_t ring_n; // completions published to the host
+    uint32_t done;   // entries whose walk has ended
+    uint32_t busy;   // waves walking now
+    uint32_t pad[3];
+    uint32_t seq[kTailCap];
+    uint32_t g[kTailCap], loc[kTailCap];
+    double t[kTailCap];
+};
+
 struct RoundArgs {
     Ctl *ctl;
     const JobDev *jobs;
@@ -1048,7 +1106,39 @@ struct RoundArgs {
     uint32_t n_cap;    // slots of each act array (main queue from the bottom, solo queue from the top)
     uint32_t solo_max; // multi-job runs: jobs with at most this many live lineages turn solo (0: never)
     double solo_step;  // horizon advance per round of a solo job
+    TailQ *tail;       // servers with a tail lane, else null
+    uint32_t tail_walkers; // waves of the tail lane: hand-offs never wait for one
 };
+
+// A lineage goes to the tail lane only if its job's speciation probability
+// leaves it a long expected walk (1 / nu events, at least this many): short
+// tails finish in the rounds as well as anywhere.
+constexpr uint64_t kTailMinWalk = 16384;
+
+// Hands solo lineage g of job jb (its state (loc, t) after its round) to the
+// tail lane if it is the job's last one and a slot is free.  The live count
+// only falls, so reading 1 while g is live means g is the last.  One lane.
+__device__ __forceinline__ bool tail_handoff(const RoundArgs &A, uint32_t jb, uint32_t g, uint32_t loc, double t) {
+    TailQ *T = A.tail;
+    if (__hip_atomic_load(&A.js[jb].remaining, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 1u) return false;
+    if (A.jobs[jb].nu_thresh > (1ull << 53) / kTailMinWalk) return false;
+    uint32_t push = ld_agent(&T->push);
+    while (true) {
+        if (push - ld_agent(&T->done) >= A.tail_walkers) return false; // every walker busy
+        const uint32_t sq = ld_agent(&T->seq[push % kTailCap]);
+        if (sq != (push < kTailCap ? 0u : ((push - kTailCap + 1u) | kTailCopied))) return false; // slot busy
+        const uint32_t seen = atomicCAS(&T->push, push, push + 1u);
+        if (seen == push) break;
+        push = seen;
+    }
+    const uint32_t i = push % kTailCap;
+    T->g[i] = g;
+    T->loc[i] = loc;
+    T->t[i] = t;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    st_agent(&T->seq[i], push + 1u);
+    return true;
+}
 
 // Horizon of job jb in round r: its schedule by age, or, once the job has
 // turned solo, a fixed advance per round from the horizon it had then.  A
@@ -1509,9 +1599,10 @@ __device__ __forceinline__ void round_group(const RoundArgs &A, uint32_t r, uint
         // a group leader retires either the candidate it merged at pickup or its speciated lineage
         const bool dead_leader = finish_dead && leader;
         wave_retire(ctl, A.js, A.ring, A.ring_cap, r, retire || dead_leader, retire ? retire_jb : jb);
-        const bool to_solo = !kSingleJob && finish_live && leader && route_solo(A, r, jb, horizon);
+        const bool to_tail = !kSingleJob && solo && finish_live && leader && A.tail && tail_handoff(A, jb, g, p.loc, t);
+        const bool to_solo = !kSingleJob && finish_live && leader && !to_tail && route_solo(A, r, jb, horizon);
         if (to_solo) push_solo(A, &ctl->solo[qout], act_out, g);
-        wave_push(q, finish_live && leader && !to_solo, g, obuf, &ctl->count[qout], act_out);
+        wave_push(q, finish_live && leader && !to_solo && !to_tail, g, obuf, &ctl->count[qout], act_out);
     }
     wave_flush(q, obuf, &ctl->count[qout], act_out);
 }
@@ -1614,13 +1705,6 @@ struct RunArgs {
 struct RoundCtl {
     uint32_t r, n_main, n_solo, stop;
 };
-
-__device__ __forceinline__ uint32_t ld_agent(const uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(uint32_t *p, uint32_t x) {
-    __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // The round control words as the host-side set-up left them (launch start).
 __device__ __forceinline__ RoundCtl read_round_ctl(Ctl *ctl, bool single) {
@@ -1800,8 +1884,131 @@ __global__ void k_run_reset(Ctl *ctl) {
 // Once a round has left no survivors the run is over (stop = kStopDone): the
 // rounds enqueued past it leave the round number and the status word alone,
 // so the host reads the true last round however late it polls.
+// Tail lane kernel: each wave claims ready entries of the tail queue one at a
+// time and walks the lineage with lanes 0-7 (its table read through the scalar
+// cache) to its speciation or a runaway search, writes the lineage's result
+// and retires it; the lane that retires a job's last lineage publishes the job
+// on the host ring, entry k as ((k + 1) << 32) | job slot.  A wave leaves when
+// it has had nothing to claim for idle_ticks while no wave walked, or when it
+// sees the host's stop word (a walk checks it every 4096 events): waves stay
+// for new hand-offs while any walk lasts, the kernel ends once the lane is
+// idle, and the host starts it again when hand-offs come.  Launched with
+// enough dynamic LDS that no round workgroup fits beside it on its compute
+// unit, so the walks do not share SIMDs with the main queue's waves.
+struct TailArgs {
+    Ctl *ctl;
+    const JobDev *jobs;
+    JobState *js;
+    Lin lin;
+    TailQ *q;
+    unsigned long long *ring_host; // host-mapped, ring_cap entries
+    uint32_t ring_cap;
+    const uint32_t *stop_host;     // host-mapped
+    unsigned long long idle_ticks;
+    uint32_t lds_entries;          // table entries each wave may copy to its part of the LDS
+};
+
+// One walk of the tail lane (lanes 0-7 of a wave): lineage g of job jb from
+// (loc0, t0) to its speciation or a runaway search, its result written and
+// the lineage retired; the job's completion goes to the host ring.
+template <bool kLds, bool kUni>
+__device__ __forceinline__ void tail_walk(const TailArgs &A, const JobView &v, uint32_t g, uint32_t jb, uint32_t loc0,
+                                          double t0, uint32_t gl, uint32_t grp_base) {
+    TailQ *T = A.q;
+    Pos p = pos_from_loc(v, loc0);
+    double t = t0;
+    uint2 row = table_row<kLds, kUni>(v, p);
+    Counters cnt;
+    uint32_t ev = 0, st = kStepOk, at = p.loc;
+    bool stopped = false;
+    do {
+        ++ev;
+        at = p.loc;
+        st = group_step<kLds, kUni>(v, p, t, row, gl, grp_base, cnt);
+        if (__builtin_expect(st == kStepSlow, 0)) {
+            t = next_event_time_group(v, p.loc, t, gl, grp_base, &A.ctl->error, cnt);
+            st = t < 0.0 ? kStepSlow : kStepOk; // kStepSlow now marks a runaway search
+        }
+        if ((ev & 4095u) == 0u && __hip_atomic_load(A.stop_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) {
+            stopped = true;
+            break;
+        }
+    } while (st == kStepOk);
+    if (stopped || gl != 0u) return;
+    const bool speciated = st == kStepSpeciated;
+    const uint32_t sloc = speciated ? at : p.loc;
+    A.lin.species[g] = speciated ? species_of(v, sloc, t) : 0ull;
+    A.lin.spec_loc[g] = sloc;
+    A.lin.spec_t[g] = t;
+    A.lin.events[g] += ev;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (atomicSub(&A.js[jb].remaining, 1u) == 1u) {
+        A.js[jb].done_round = ld_agent(&A.ctl->round);
+        const uint32_t k = atomicAdd(&T->ring_n, 1u);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&A.ring_host[k % A.ring_cap], ((unsigned long long)(k + 1u) << 32) | jb, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    atomicAdd(&T->done, 1u);
+}
+
+__global__ __launch_bounds__(256) void k_tail(TailArgs A) {
+    const uint32_t lane = lane_id(), gl = lane & (kGroup - 1), grp_base = lane & ~(kGroup - 1);
+    TailQ *T = A.q;
+    unsigned long long idle_from = wall_clock64();
+    for (uint32_t poll = 0;; ++poll) {
+        uint32_t take = 0, got = 0, stop = 0;
+        if (lane == 0) {
+            // the stop word lives in host memory: read it seldom (every 32nd poll, about 0.1 ms)
+            if ((poll & 31u) == 0u) stop = __hip_atomic_load(A.stop_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            take = ld_agent(&T->take);
+            if (!stop && ld_agent(&T->seq[take % kTailCap]) == take + 1u)
+                got = atomicCAS(&T->take, take, take + 1u) == take ? 1u : 0u;
+        }
+        stop = (uint32_t)__builtin_amdgcn_readfirstlane(stop);
+        got = (uint32_t)__builtin_amdgcn_readfirstlane(got);
+        take = (uint32_t)__builtin_amdgcn_readfirstlane(take);
+        if (stop) break;
+        if (!got) {
+            if (wall_clock64() - idle_from > A.idle_ticks && ld_agent(&T->busy) == 0u) break;
+            __builtin_amdgcn_s_sleep(127); // about 3 us between polls
+            continue;
+        }
+        if (lane == 0) atomicAdd(&T->busy, 1u);
+        const uint32_t i = take % kTailCap;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const uint32_t g = T->g[i], loc0 = T->loc[i];
+        const double t0 = T->t[i];
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) st_agent(&T->seq[i], (take + 1u) | kTailCopied);
+        {
+            const uint32_t jb = A.lin.job[g];
+            JobView v = load_view(&A.jobs[jb]);
+            // a shared table that fits the wave's part of the LDS is copied there (the wave's 64 lanes),
+            // else read through the scalar cache
+            const bool stage = v.mode == NH_DISPERSAL_SHARED && v.n_shared <= A.lds_entries;
+            if (stage) {
+                v.lds_base = (threadIdx.x / 64) * A.lds_entries;
+                for (uint32_t e = lane; e < v.n_shared; e += 64) nh_lds_table[v.lds_base + e] = v.table[e];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            if (lane < kGroup) {
+                if (stage) tail_walk<true, false>(A, v, g, jb, loc0, t0, gl, grp_base);
+                else tail_walk<false, true>(A, v, g, jb, loc0, t0, gl, grp_base);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) atomicSub(&T->busy, 1u);
+        idle_from = wall_clock64();
+    }
+}
+
+// tail/tail_host (servers with a tail lane): the count of tail hand-offs is
+// copied to the host-mapped word, where the host sees that the lane has work.
 __global__ void k_advance(Ctl *ctl, unsigned long long *status_host, const uint32_t *ring, uint32_t ring_cap,
-                          uint32_t *ring_host) {
+                          uint32_t *ring_host, const TailQ *tail = nullptr, uint32_t *tail_host = nullptr) {
     if (ctl->stop == kStopDone) return;
     const uint32_t r = ctl->round;
     const uint32_t n_out = ctl->count[(r + 1) % 3] + ctl->solo[(r + 1) % 3];
@@ -1811,6 +2018,9 @@ __global__ void k_advance(Ctl *ctl, unsigned long long *status_host, const uint3
     ctl->solo_cursor[(r + 1) % 3] = 0;
     ctl->cursor[(r + 1) % 3] = 0;
     ctl->round = r + 1;
+    if (tail_host)
+        __hip_atomic_store(tail_host, __hip_atomic_load(&tail->push, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     if (ring_host) {
         const uint32_t head = ctl->ring_head;
         for (uint32_t i = ctl->ring_pub; i != head; ++i)
@@ -3896,15 +4106,37 @@ struct nh_server {
     uint32_t ring_read = 0;
     uint32_t active = 0, resolving = 0;
     uint64_t rounds_enqueued = 0;
+    uint64_t admitted_at = 0; // rounds enqueued when the last job was admitted (its k_init follows them)
     uint32_t grid = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // tail lane
+    uint32_t tail_blocks = 0;
+    size_t tail_lds = 0;
+    hipStream_t tail_stream = nullptr;
+    hipEvent_t tail_ev = nullptr;
+    TailQ *d_tail = nullptr;
+    unsigned long long *tail_ring_h = nullptr, *tail_ring_d = nullptr;
+    uint32_t *tail_word_h = nullptr, *tail_word_d = nullptr; // [0]: hand-offs (copied each round), [1]: stop
+    uint32_t tail_read = 0, tail_seen = 0;
+    bool tail_launched = false;
+    unsigned long long tail_idle_ticks = 0;
 };
 
 namespace {
 
 void server_free(nh_server *s) {
     if (!s) return;
+    if (s->tail_stream) {
+        // the tail kernel leaves on the stop word (a walk within 4096 events)
+        if (s->tail_word_h) __atomic_store_n(&s->tail_word_h[1], 1u, __ATOMIC_SEQ_CST);
+        (void)hipStreamSynchronize(s->tail_stream);
+        (void)hipStreamDestroy(s->tail_stream);
+    }
+    if (s->tail_ev) (void)hipEventDestroy(s->tail_ev);
+    if (s->d_tail) (void)hipFree(s->d_tail);
+    if (s->tail_ring_h) (void)hipHostFree(s->tail_ring_h);
+    if (s->tail_word_h) (void)hipHostFree(s->tail_word_h);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     for (auto &sl : s->slots)
         if (sl.ev) (void)hipEventDestroy(sl.ev);
@@ -3962,11 +4194,103 @@ void job_descriptor(JobDev &d, const nh_job &job, unsigned long long *rich_set, 
     d.start_round = 0;
 }
 
+// The tail lane's queue, host ring and words, its stream, and the LDS a tail
+// workgroup takes so that no round workgroup (which needs a few KiB) fits on
+// its compute unit.  tail_blocks == 0 (or no solo jobs): no lane.
+int server_tail_setup(nh_server *s, uint32_t tail_blocks) {
+    if (tail_blocks == 0 || s->cfg.solo_max == 0 || s->grid < 4) return NH_OK;
+    s->tail_blocks = std::min<uint32_t>(tail_blocks, 64);
+    int lds_cu = 0, lds_block = 0, khz = 0;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, s->device) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device) != hipSuccess || khz <= 0)
+        return fail(NH_EDEVICE, "device query failed");
+    s->tail_lds = (size_t)std::max(0, std::min(lds_cu, lds_block));
+    if (s->tail_lds > 65536 &&
+        hipFuncSetAttribute((const void *)k_tail, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s->tail_lds) !=
+            hipSuccess)
+        s->tail_lds = 65536;
+    s->tail_idle_ticks = (unsigned long long)khz / 5; // 200 us
+    if (hipMalloc(&s->d_tail, sizeof(TailQ)) != hipSuccess) return fail(NH_ENOMEM, "tail queue allocation failed");
+    if (hipMemsetAsync(s->d_tail, 0, sizeof(TailQ), s->stream) != hipSuccess)
+        return fail(NH_EDEVICE, "tail queue clear failed");
+    void *h = nullptr;
+    if (hipHostMalloc(&h, sizeof(unsigned long long) * s->max_jobs, hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
+        return fail(NH_ENOMEM, "pinned tail ring allocation failed");
+    s->tail_ring_h = (unsigned long long *)h;
+    std::memset(s->tail_ring_h, 0, sizeof(unsigned long long) * s->max_jobs);
+    if (hipHostGetDevicePointer((void **)&s->tail_ring_d, h, 0) != hipSuccess)
+        return fail(NH_EDEVICE, "tail ring mapping failed");
+    if (hipHostMalloc(&h, 64, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+        return fail(NH_ENOMEM, "pinned tail word allocation failed");
+    s->tail_word_h = (uint32_t *)h;
+    std::memset(s->tail_word_h, 0, 64);
+    if (hipHostGetDevicePointer((void **)&s->tail_word_d, h, 0) != hipSuccess)
+        return fail(NH_EDEVICE, "tail word mapping failed");
+    if (hipStreamCreateWithFlags(&s->tail_stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(NH_EDEVICE, "tail stream creation failed");
+    if (hipEventCreateWithFlags(&s->tail_ev, hipEventDisableTiming) != hipSuccess)
+        return fail(NH_EDEVICE, "tail event creation failed");
+    return NH_OK;
+}
+
+// Starts the tail kernel when hand-offs have come since its last start and it
+// has left: every entry filled before a start is seen by that kernel, which
+// only leaves after idle_ticks with nothing ready.
+int server_tail_kick(nh_server *s) {
+    if (!s->tail_stream) return NH_OK;
+    const uint32_t pushed = __atomic_load_n(&s->tail_word_h[0], __ATOMIC_ACQUIRE);
+    if (pushed == s->tail_seen) return NH_OK;
+    if (s->tail_launched) {
+        const hipError_t q = hipEventQuery(s->tail_ev);
+        if (q == hipErrorNotReady) return NH_OK;
+        if (q != hipSuccess) return fail(NH_EDEVICE, "tail lane failed: %s", hipGetErrorString(q));
+    }
+    s->tail_seen = pushed;
+    TailArgs ta;
+    ta.ctl = s->ctl;
+    ta.jobs = s->d_jobs;
+    ta.js = s->d_js;
+    ta.lin = s->lin;
+    ta.q = s->d_tail;
+    ta.ring_host = s->tail_ring_d;
+    ta.ring_cap = s->max_jobs;
+    ta.stop_host = s->tail_word_d + 1;
+    ta.idle_ticks = s->tail_idle_ticks;
+    ta.lds_entries = (uint32_t)(s->tail_lds / (4 * sizeof(uint4)));
+    k_tail<<<s->tail_blocks, 256, s->tail_lds, s->tail_stream>>>(ta);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(s->tail_ev, s->tail_stream));
+    s->tail_launched = true;
+    return NH_OK;
+}
+
 int server_launch_round(nh_server *s) {
     if (s->exec) HIP_TRY(hipGraphLaunch(s->exec, s->stream));
     else return fail(NH_EDEVICE, "server round graph missing");
     HIP_TRY(hipGetLastError());
     s->rounds_enqueued += s->cfg.rounds_per_graph;
+    return NH_OK;
+}
+
+// Output of a completed job, enqueued on the server stream.
+int server_resolve(nh_server *s, uint32_t slot) {
+    ServerSlot &sl = s->slots[slot];
+    const uint32_t blocks = (uint32_t)((sl.n + 255) / 256);
+    k_resolve<<<blocks, 256, 0, s->stream>>>(s->d_jobs, s->d_js, s->lin, (uint32_t)sl.lin_base,
+                                              (uint32_t)(sl.lin_base + sl.n), nullptr);
+    if (sl.job.d_abundance_counts_out)
+        k_abundance<<<(uint32_t)((sl.rich_slots + 255) / 256), 256, 0, s->stream>>>(s->d_jobs, s->d_js, slot, slot + 1,
+                                                                                  sl.rich_slots, nullptr);
+    k_finalize<<<1, 1, 0, s->stream>>>(s->d_jobs, s->d_js, slot, slot + 1, nullptr, 0u);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(&s->js_h[slot], &s->d_js[slot], sizeof(JobState), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipEventRecord(sl.ev, s->stream));
+    sl.state = kSlotResolving;
+    --s->active;
+    ++s->resolving;
     return NH_OK;
 }
 
@@ -4011,6 +4335,7 @@ int server_admit(nh_server *s, const nh_job &job, uint64_t tag, bool &admitted) 
     }
     HIP_TRY(hipGetLastError());
     ++s->active;
+    s->admitted_at = s->rounds_enqueued;
     admitted = true;
     return NH_OK;
 }
@@ -4129,6 +4454,9 @@ NH_API int nh_server_create(const nh_server_config *config, void *stream, nh_ser
     ra.n_cap = (uint32_t)s->cap_lin;
     ra.solo_max = s->grid < 4 ? 0u : s->cfg.solo_max; // solo blocks never take more than a quarter
     ra.solo_step = s->cfg.solo_step;
+    if (int rc = server_tail_setup(s, config->tail_blocks)) return bail(rc);
+    ra.tail = s->d_tail;
+    ra.tail_walkers = s->tail_blocks * 4;
     hipStream_t cap_stream;
     if (hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(NH_EDEVICE, "capture stream creation failed"));
@@ -4136,7 +4464,8 @@ NH_API int nh_server_create(const nh_server_config *config, void *stream, nh_ser
     if (e == hipSuccess) {
         for (uint32_t k = 0; k < s->cfg.rounds_per_graph; ++k) {
             k_round<false, false><<<s->grid, s->cfg.block_size, 0, cap_stream>>>(ra);
-            k_advance<<<1, 1, 0, cap_stream>>>(s->ctl, s->status_d, s->d_ring, s->max_jobs, s->ring_hd);
+            k_advance<<<1, 1, 0, cap_stream>>>(s->ctl, s->status_d, s->d_ring, s->max_jobs, s->ring_hd, s->d_tail,
+                                               s->d_tail ? s->tail_word_d : nullptr);
         }
         e = hipStreamEndCapture(cap_stream, &s->graph);
     }
@@ -4171,21 +4500,19 @@ NH_API int nh_server_progress(nh_server *s, uint32_t *active_out, uint32_t *pend
         ++s->ring_read;
         if (slot >= s->max_jobs || s->slots[slot].state != kSlotActive)
             return fail(NH_EDEVICE, "corrupt completion ring entry %u", slot);
-        ServerSlot &sl = s->slots[slot];
-        const uint32_t blocks = (uint32_t)((sl.n + 255) / 256);
-        k_resolve<<<blocks, 256, 0, s->stream>>>(s->d_jobs, s->d_js, s->lin, (uint32_t)sl.lin_base,
-                                                  (uint32_t)(sl.lin_base + sl.n), nullptr);
-        if (sl.job.d_abundance_counts_out)
-            k_abundance<<<(uint32_t)((sl.rich_slots + 255) / 256), 256, 0, s->stream>>>(s->d_jobs, s->d_js, slot,
-                                                                                      slot + 1, sl.rich_slots, nullptr);
-        k_finalize<<<1, 1, 0, s->stream>>>(s->d_jobs, s->d_js, slot, slot + 1, nullptr, 0u);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipMemcpyAsync(&s->js_h[slot], &s->d_js[slot], sizeof(JobState), hipMemcpyDeviceToHost, s->stream));
-        HIP_TRY(hipEventRecord(sl.ev, s->stream));
-        sl.state = kSlotResolving;
-        --s->active;
-        ++s->resolving;
+        if (int rc = server_resolve(s, slot)) return rc;
     }
+    // (a') completions published by the tail lane
+    while (s->tail_ring_h) {
+        const unsigned long long e = __atomic_load_n(&s->tail_ring_h[s->tail_read % s->max_jobs], __ATOMIC_ACQUIRE);
+        if ((uint32_t)(e >> 32) != s->tail_read + 1u) break;
+        const uint32_t slot = (uint32_t)e;
+        ++s->tail_read;
+        if (slot >= s->max_jobs || s->slots[slot].state != kSlotActive)
+            return fail(NH_EDEVICE, "corrupt tail ring entry %u", slot);
+        if (int rc = server_resolve(s, slot)) return rc;
+    }
+    if (int rc = server_tail_kick(s)) return rc;
     // (b) resolved jobs: report, free their slots and ranges
     if (s->resolving) {
         for (uint32_t k = 0; k < s->max_jobs; ++k) {
@@ -4225,13 +4552,16 @@ NH_API int nh_server_progress(nh_server *s, uint32_t *active_out, uint32_t *pend
             ++k;
         }
     }
-    // (d) rounds: keep two launches in flight while jobs are active
+    // (d) rounds: keep two launches in flight while lineages are in the rounds (the last round
+    // left some queued, or a job was admitted after the rounds enqueued so far); jobs whose last
+    // lineage walks in the tail lane need none
     if (s->active) {
         const unsigned long long word = __atomic_load_n(s->status_h, __ATOMIC_ACQUIRE);
         if ((word >> 31) & 1u) return fail(NH_EDEVICE, "kernel reported an error");
         const uint32_t next_round = (uint32_t)(word >> 32);
         const uint64_t completed = next_round >= 1 ? next_round - 1 : 0;
-        while (s->rounds_enqueued < completed + 2ull * s->cfg.rounds_per_graph)
+        const bool queued = (word & 0x7FFFFFFFull) != 0 || completed <= s->admitted_at;
+        while (queued && s->rounds_enqueued < completed + 2ull * s->cfg.rounds_per_graph)
             if (int rc = server_launch_round(s)) return rc;
     }
     if (active_out) *active_out = s->active + s->resolving;

@@ -73,7 +73,7 @@ def table_bytes_estimate(spec: dict) -> int:
 def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, lineage_capacity: int | None = None,
                max_jobs: int = 2048, lookahead: int = 64, config=None, workers: int = 4, timeout_s: float = 900.0,
                collect: bool = False, measure_from: float = 0.0, table_frac: float = 0.02,
-               progress_s: float = 0.0):
+               progress_s: float = 0.0, tail_blocks: int = 32):
     """Serve the stream; returns latency percentiles, throughput and admission statistics.
 
     HBM admission: the budget (default half of the free HBM) holds the resident lineage pool (the
@@ -81,6 +81,8 @@ def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, linea
     tables; a request whose tables would not fit waits, unbuilt, until completed requests release
     theirs, and a request is admitted into the running batch once its lineage slots are free.
     progress_s > 0: a line on stderr that often (requests done, active, waiting).
+    tail_blocks: compute units of the server's tail lane (a job's last lineage walks there outside
+    the rounds; 0 = none).
     measure_from: requests arriving before this time (s) warm the server up and are left out of
     the latency and throughput figures.  collect: also return each request's result as (richness,
     SHA-256 of its species array in sample order), read back on completion (for parity checks; it
@@ -98,7 +100,8 @@ def run_served(arrivals, requests, *, hbm_budget_bytes: int | None = None, linea
         lineage_capacity = lineage_capacity_for_budget(hbm_budget_bytes - table_budget, max_jobs)
     pool_bytes = B.server_bytes(lineage_capacity, max_jobs)
     stream = torch.cuda.Stream()
-    srv = B.Server(lineage_capacity, max_jobs=max_jobs, lookahead=lookahead, config=config, stream=stream)
+    srv = B.Server(lineage_capacity, max_jobs=max_jobs, lookahead=lookahead, config=config, stream=stream,
+                   tail_blocks=tail_blocks)
     pool = cf.ThreadPoolExecutor(max_workers=workers)
     n = len(requests)
     lat = np.full(n, np.nan)

@@ -43,10 +43,11 @@ def _mix():
     return wl
 
 
-SOLO = [None, (256, 64.0), (1 << 30, 8.0)]
+SOLO = [None, (256, 64.0), (1 << 30, 8.0), (256, 64.0, 4), (16, 512.0, 1)]
 
 
-@pytest.mark.parametrize("solo", SOLO, ids=["default", "solo 256 step 64", "all solo step 8"])
+@pytest.mark.parametrize("solo", SOLO, ids=["default", "solo 256 step 64", "all solo step 8",
+                                             "solo 256 step 64 tail lane 4", "solo 16 tail lane 1"])
 def test_served_results_equal_alone_and_oracle(env, solo):
     B, torch = env
     dev = torch.device("cuda:0")
@@ -56,7 +57,8 @@ def test_served_results_equal_alone_and_oracle(env, solo):
     cfg = None if solo is None else B.make_config(solo_max=solo[0], solo_step=solo[1])
     say("solo setting", solo)
     # a pool that holds the biggest job but not everything at once: admissions must wait
-    srv = B.Server(lineage_capacity=biggest + 3000, max_jobs=8, lookahead=4, config=cfg)
+    srv = B.Server(lineage_capacity=biggest + 3000, max_jobs=8, lookahead=4, config=cfg,
+                   tail_blocks=solo[2] if solo is not None and len(solo) > 2 else 0)
     outs, submitted = {}, 0
     order = list(range(len(wls)))
     done = {}
