@@ -145,6 +145,10 @@ typedef struct {
     uint32_t barrier_wait_ms; /* persistent launches: the longest a workgroup waits at one grid barrier
                                  before it stops the run (NH_EDEVICE; the kernel exits either way);
                                  default 0: min(timeout_s, 60 s) */
+    uint32_t endgame;     /* persistent runs of several jobs: once at most this many lineages (up to
+                             4096) are left, the rounds end and each is walked to its end by a wave of
+                             its own (lineages that would still merge then walk the same events twice:
+                             the results are the same, the event counts larger); default 0: never */
 } nh_config;
 
 #define NH_LAUNCH_PERSISTENT 0u
@@ -411,7 +415,11 @@ typedef struct {
 uint64_t nh_server_bytes(uint64_t lineage_capacity, uint32_t max_jobs);
 
 /* Allocates the pool on the current device and captures the round graph.
- * stream may be NULL (the server then creates its own non-blocking stream).
+ * stream may be NULL (the server then creates its own non-blocking stream).  With a
+ * tail lane the server always runs on streams of its own (a long-running lane kernel
+ * must not share a hardware queue with the rounds); a given stream then only orders
+ * submissions: each nh_server_submit makes the server wait for the work enqueued on it
+ * so far.  Outputs are complete once the job's completion is polled.
  * Errors: NH_EINVAL for zero capacity or jobs; NH_ENOMEM; NH_EDEVICE. */
 int nh_server_create(const nh_server_config *config, void *stream, nh_server **out);
 

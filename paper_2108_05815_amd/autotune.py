@@ -57,7 +57,8 @@ def to_config(knobs: dict, n_cu: int | None = None, **extra) -> B.nh_config:
                          blocks_per_cu=knobs["blocks_per_cu"], block_size=knobs["block_size"],
                          rounds_per_graph=knobs["rounds_per_graph"], table_placement=knobs["table_placement"],
                          coop_max=(lanes // div + 1) if div else 1, launch=knobs.get("launch", 0),
-                         solo_max=knobs.get("solo_max", 0), solo_step=knobs.get("solo_step", 0.0), **extra)
+                         solo_max=knobs.get("solo_max", 0), solo_step=knobs.get("solo_step", 0.0),
+                         endgame=knobs.get("endgame", 0), **extra)
 
 
 def tune(run, knobs=None, start=None, reps: int = 3, passes: int = 1, log=None):

@@ -46,7 +46,8 @@ class nh_config(C.Structure):
                 ("block_size", C.c_uint32), ("blocks_per_cu", C.c_uint32), ("rounds_per_graph", C.c_uint32),
                 ("event_timing", C.c_uint32), ("coop_max", C.c_uint32), ("table_placement", C.c_uint32),
                 ("timeout_s", C.c_double), ("solo_max", C.c_uint32), ("launch", C.c_uint32),
-                ("solo_step", C.c_double), ("max_rounds", C.c_uint32), ("barrier_wait_ms", C.c_uint32)]
+                ("solo_step", C.c_double), ("max_rounds", C.c_uint32), ("barrier_wait_ms", C.c_uint32),
+                ("endgame", C.c_uint32)]
 
 
 class nh_stats(C.Structure):

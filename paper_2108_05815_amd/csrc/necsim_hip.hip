@@ -180,6 +180,7 @@ struct Ctl {
 constexpr uint32_t kStopDone = 1u;      // every lineage retired
 constexpr uint32_t kStopSuspended = 2u; // the round limit of the call was reached
 constexpr uint32_t kStopError = 3u;     // a kernel error flag, the run's time limit or a stalled barrier
+constexpr uint32_t kStopEndgame = 4u;   // few lineages are left: k_endgame walks each to its end
 constexpr uint32_t kErrTimeout = 16u;   // the run exceeded its time limit
 constexpr uint32_t kErrStall = 32u;     // a barrier wait exceeded its limit (workgroups not all resident)
 
@@ -1697,7 +1698,7 @@ __global__ __launch_bounds__(256) void k_round(RoundArgs A) {
 // ---------------------------------------------------------------------------
 struct RunArgs {
     uint32_t max_rounds;          // rounds of this launch before it suspends (0: no limit)
-    uint32_t pad;
+    uint32_t endgame;             // stop for k_endgame once at most this many lineages remain (0: never)
     unsigned long long spin_ticks; // wall-clock ticks one barrier wait may take
     unsigned long long run_ticks;  // wall-clock ticks the whole launch may take
 };
@@ -1745,6 +1746,8 @@ __device__ __forceinline__ RoundCtl run_epilogue(Ctl *ctl, const RunArgs &R) {
         stop = kStopDone;
     } else if ((err & ~kErrBadSample) != 0u) {
         stop = kStopError; // a bad sample id only fails its own job
+    } else if (n_out <= R.endgame) {
+        stop = kStopEndgame;
     } else if (R.max_rounds != 0u && r + 1u - first >= R.max_rounds) {
         stop = kStopSuspended;
     } else if (wall_clock64() - run_start(ctl) > R.run_ticks) {
@@ -1908,39 +1911,75 @@ struct TailArgs {
     uint32_t lds_entries;          // table entries each wave may copy to its part of the LDS
 };
 
-// One walk of the tail lane (lanes 0-7 of a wave): lineage g of job jb from
-// (loc0, t0) to its speciation or a runaway search, its result written and
-// the lineage retired; the job's completion goes to the host ring.
+// A lone lineage's walk to its end (lanes 0-7 of a wave; the group's lanes
+// agree throughout): from (p, t) event after event, with no horizon, until it
+// speciates (kStepSpeciated; at = the event's location, t its time) or the
+// search runs away (kStepSlow, flagged in err).  Every 4096 events the walk
+// reads *stop (when given) and the wall clock (when a deadline is given) and
+// returns kStepOk if either says so.  ev counts the events.
+template <bool kLds, bool kUni>
+__device__ __forceinline__ uint32_t walk_to_end(const JobView &v, Pos &p, double &t, uint32_t &at, uint32_t &ev,
+                                                uint32_t gl, uint32_t grp_base, uint32_t *err, const uint32_t *stop,
+                                                unsigned long long deadline) {
+    uint2 row = table_row<kLds, kUni>(v, p);
+    Counters cnt;
+    uint32_t st = kStepOk;
+    do {
+        ++ev;
+        at = p.loc;
+        st = group_step<kLds, kUni>(v, p, t, row, gl, grp_base, cnt);
+        if (__builtin_expect(st == kStepSlow, 0)) {
+            t = next_event_time_group(v, p.loc, t, gl, grp_base, err, cnt);
+            st = t < 0.0 ? kStepSlow : kStepOk; // kStepSlow now marks a runaway search
+        }
+        if ((ev & 4095u) == 0u) {
+            if (stop && __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) return kStepOk;
+            if (deadline && wall_clock64() > deadline) {
+                atomicOr(err, kErrTimeout);
+                return kStepOk;
+            }
+        }
+    } while (st == kStepOk);
+    return st;
+}
+
+// Writes the end of lineage g's walk (a speciation or a runaway search) into the
+// lineage arrays.  One lane.
+__device__ __forceinline__ void write_walk_end(const Lin &lin, const JobView &v, uint32_t g, uint32_t st, uint32_t at,
+                                               const Pos &p, double t, uint32_t ev) {
+    const bool speciated = st == kStepSpeciated;
+    const uint32_t sloc = speciated ? at : p.loc;
+    lin.species[g] = speciated ? species_of(v, sloc, t) : 0ull;
+    lin.spec_loc[g] = sloc;
+    lin.spec_t[g] = t;
+    lin.events[g] += ev;
+}
+
+// Copies the shared dispersal table of v into this wave's part of the LDS
+// (entries per wave, wave w of the workgroup from w * entries) when it fits;
+// returns whether it did (then v reads it there).
+__device__ __forceinline__ bool stage_wave_table(JobView &v, uint32_t entries) {
+    if (!(v.mode == NH_DISPERSAL_SHARED && v.n_shared <= entries)) return false;
+    v.lds_base = (threadIdx.x / 64) * entries;
+    for (uint32_t e = lane_id(); e < v.n_shared; e += 64) nh_lds_table[v.lds_base + e] = v.table[e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return true;
+}
+
+// One walk of the tail lane: lineage g of job jb from (loc0, t0), its result
+// written and the lineage retired; the job's completion goes to the host ring.
 template <bool kLds, bool kUni>
 __device__ __forceinline__ void tail_walk(const TailArgs &A, const JobView &v, uint32_t g, uint32_t jb, uint32_t loc0,
                                           double t0, uint32_t gl, uint32_t grp_base) {
     TailQ *T = A.q;
     Pos p = pos_from_loc(v, loc0);
     double t = t0;
-    uint2 row = table_row<kLds, kUni>(v, p);
-    Counters cnt;
-    uint32_t ev = 0, st = kStepOk, at = p.loc;
-    bool stopped = false;
-    do {
-        ++ev;
-        at = p.loc;
-        st = group_step<kLds, kUni>(v, p, t, row, gl, grp_base, cnt);
-        if (__builtin_expect(st == kStepSlow, 0)) {
-            t = next_event_time_group(v, p.loc, t, gl, grp_base, &A.ctl->error, cnt);
-            st = t < 0.0 ? kStepSlow : kStepOk; // kStepSlow now marks a runaway search
-        }
-        if ((ev & 4095u) == 0u && __hip_atomic_load(A.stop_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) {
-            stopped = true;
-            break;
-        }
-    } while (st == kStepOk);
-    if (stopped || gl != 0u) return;
-    const bool speciated = st == kStepSpeciated;
-    const uint32_t sloc = speciated ? at : p.loc;
-    A.lin.species[g] = speciated ? species_of(v, sloc, t) : 0ull;
-    A.lin.spec_loc[g] = sloc;
-    A.lin.spec_t[g] = t;
-    A.lin.events[g] += ev;
+    uint32_t at = p.loc, ev = 0;
+    const uint32_t st = walk_to_end<kLds, kUni>(v, p, t, at, ev, gl, grp_base, &A.ctl->error, A.stop_host, 0ull);
+    if (st == kStepOk || gl != 0u) return; // stopped by the host (the server is going away)
+    write_walk_end(A.lin, v, g, st, at, p, t, ev);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (atomicSub(&A.js[jb].remaining, 1u) == 1u) {
         A.js[jb].done_round = ld_agent(&A.ctl->round);
@@ -1950,6 +1989,45 @@ __device__ __forceinline__ void tail_walk(const TailArgs &A, const JobView &v, u
                            __HIP_MEMORY_SCOPE_SYSTEM);
     }
     atomicAdd(&T->done, 1u);
+}
+
+// Endgame of a persistent multi-job run (the launch stopped with
+// kStopEndgame): the few lineages queued for the next round are walked to
+// their ends independently, one wave each (lanes 0-7), with the shared table
+// staged in the wave's part of the LDS when it fits, else read through the
+// scalar cache.  Lineages that would still have merged walk the same events
+// twice and reach the same species (an individual's species is a function of
+// its own path alone), so only the event counts see the difference.  Wave w
+// takes queue item w: the main queue first, then the solo queue from the top.
+// A walk that passes the run's deadline flags kErrTimeout and stops.
+__global__ __launch_bounds__(256) void k_endgame(RoundArgs A, unsigned long long run_ticks, uint32_t lds_entries) {
+    Ctl *ctl = A.ctl;
+    if (ld_agent(&ctl->stop) != kStopEndgame) return;
+    const uint32_t r = ld_agent(&ctl->round);
+    const uint32_t n_main = ld_agent(&ctl->count[r % 3]), n_solo = ld_agent(&ctl->solo[r % 3]);
+    const uint32_t w = (blockIdx.x * blockDim.x + threadIdx.x) / 64, lane = lane_id();
+    if (w >= n_main + n_solo) return;
+    const uint32_t *act = A.lin.act[r & 1];
+    const uint32_t g = w < n_main ? act[w] : act[A.n_cap - 1u - (w - n_main)];
+    const uint32_t jb = A.lin.job[g];
+    JobView v = load_view(&A.jobs[jb]);
+    const bool stage = stage_wave_table(v, lds_entries);
+    if (lane >= kGroup) return;
+    Pos p = pos_from_loc(v, A.lin.loc[r & 1][g]);
+    double t = A.lin.t[r & 1][g];
+    uint32_t at = p.loc, ev = 0;
+    const unsigned long long deadline = run_start(ctl) + run_ticks;
+    const uint32_t st = stage ? walk_to_end<true, false>(v, p, t, at, ev, lane, 0u, &ctl->error, nullptr, deadline)
+                              : walk_to_end<false, true>(v, p, t, at, ev, lane, 0u, &ctl->error, nullptr, deadline);
+    if (st == kStepOk || lane != 0u) return; // past the deadline (flagged)
+    write_walk_end(A.lin, v, g, st, at, p, t, ev);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    job_retired(ctl, A.js, A.ring, A.ring_cap, r, jb, 1u);
+}
+
+// After k_endgame: the run is over (unless a walk timed out).
+__global__ void k_endgame_done(Ctl *ctl) {
+    if (ctl->stop == kStopEndgame && (ctl->error & kErrTimeout) == 0u) ctl->stop = kStopDone;
 }
 
 __global__ __launch_bounds__(256) void k_tail(TailArgs A) {
@@ -1986,14 +2064,7 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs A) {
             JobView v = load_view(&A.jobs[jb]);
             // a shared table that fits the wave's part of the LDS is copied there (the wave's 64 lanes),
             // else read through the scalar cache
-            const bool stage = v.mode == NH_DISPERSAL_SHARED && v.n_shared <= A.lds_entries;
-            if (stage) {
-                v.lds_base = (threadIdx.x / 64) * A.lds_entries;
-                for (uint32_t e = lane; e < v.n_shared; e += 64) nh_lds_table[v.lds_base + e] = v.table[e];
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
+            const bool stage = stage_wave_table(v, A.lds_entries);
             if (lane < kGroup) {
                 if (stage) tail_walk<true, false>(A, v, g, jb, loc0, t0, gl, grp_base);
                 else tail_walk<false, true>(A, v, g, jb, loc0, t0, gl, grp_base);
@@ -3186,9 +3257,10 @@ int persistent_grid(const PersistentLane &L, uint32_t variant, const nh_config &
 // reset the barrier state, then k_run on the device's persistent stream.
 // t0/t1 (nullable) bracket the run kernel alone.
 int enqueue_persistent(PersistentLane &L, uint32_t variant, const RoundArgs &ra, const nh_config &cfg, size_t lds,
-                       uint32_t grid, hipStream_t stream, hipEvent_t t0, hipEvent_t t1) {
+                       uint32_t grid, hipStream_t stream, hipEvent_t t0, hipEvent_t t1, uint32_t endgame = 0) {
     RunArgs R{};
     R.max_rounds = cfg.max_rounds;
+    R.endgame = endgame;
     const double khz = (double)L.clock_khz;
     const double wait_s = cfg.barrier_wait_ms ? cfg.barrier_wait_ms * 1e-3 : std::min(cfg.timeout_s, 60.0);
     R.spin_ticks = (unsigned long long)std::max(1.0, wait_s * khz * 1e3);
@@ -3209,6 +3281,21 @@ int enqueue_persistent(PersistentLane &L, uint32_t variant, const RoundArgs &ra,
     HIP_TRY(hipEventRecord(L.out, L.stream));
     HIP_TRY(hipStreamWaitEvent(stream, L.out, 0));
     return NH_OK;
+}
+
+// Dynamic LDS of a one-wave-per-lineage walk kernel (k_tail, k_endgame): all
+// the LDS a workgroup may take (so it holds a compute unit alone), opted in
+// once per kernel past the default 64 KiB limit.
+size_t walk_kernel_lds(const void *kernel) {
+    int dev = 0, lds_cu = 0, lds_block = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 0;
+    size_t bytes = (size_t)std::max(0, std::min(lds_cu, lds_block));
+    if (bytes > 65536 && hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+        bytes = 65536;
+    return bytes;
 }
 
 // Workspace of nh_simulate_noalloc: a file-scope device array, one copy per
@@ -3542,7 +3629,17 @@ int batch_run_impl(const nh_job *jobs, uint32_t n_jobs, void *d_workspace, uint6
             t1 = ev_pool[1];
             ev_used = 1;
         }
-        if (int rc = enqueue_persistent(*lane, variant, ra, cfg, lds_bytes, grid, stream, t0, t1)) return rc;
+        // a batch of several jobs ends with the endgame (the few last lineages walked to their ends)
+        const uint32_t endgame = single ? 0u : std::min<uint32_t>(cfg.endgame, 4096u);
+        if (int rc = enqueue_persistent(*lane, variant, ra, cfg, lds_bytes, grid, stream, t0, t1, endgame)) return rc;
+        if (endgame) {
+            static const size_t end_lds = walk_kernel_lds((const void *)k_endgame);
+            const double khz = (double)lane->clock_khz;
+            const unsigned long long run_ticks = (unsigned long long)std::max(1.0, cfg.timeout_s * khz * 1e3);
+            k_endgame<<<(endgame + 3) / 4, 256, end_lds, stream>>>(ra, run_ticks,
+                                                                    (uint32_t)(end_lds / (4 * sizeof(uint4))));
+            k_endgame_done<<<1, 1, 0, stream>>>(ctl);
+        }
         const uint32_t blocks = (uint32_t)((n_total + 255) / 256);
         k_resolve<<<blocks, 256, 0, stream>>>(d_jobs, d_js, lin, 0, (uint32_t)n_total, ctl);
         if (any_abundance)
@@ -4077,8 +4174,10 @@ struct ServerSlot {
 
 struct nh_server {
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;        // rounds, admissions and outputs
     bool own_stream = false;
+    hipStream_t user_stream = nullptr;   // the caller's stream when the server runs its own
+    hipEvent_t submit_ev = nullptr;
     nh_config cfg{};
     uint64_t cap_lin = 0;
     uint32_t max_jobs = 0, lookahead = 0;
@@ -4147,6 +4246,7 @@ void server_free(nh_server *s) {
     if (s->ring_h) (void)hipHostFree(s->ring_h);
     if (s->js_h) (void)hipHostFree(s->js_h);
     if (s->jobdev_h) (void)hipHostFree(s->jobdev_h);
+    if (s->submit_ev) (void)hipEventDestroy(s->submit_ev);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -4198,7 +4298,7 @@ void job_descriptor(JobDev &d, const nh_job &job, unsigned long long *rich_set, 
 // workgroup takes so that no round workgroup (which needs a few KiB) fits on
 // its compute unit.  tail_blocks == 0 (or no solo jobs): no lane.
 int server_tail_setup(nh_server *s, uint32_t tail_blocks) {
-    if (tail_blocks == 0 || s->cfg.solo_max == 0 || s->grid < 4) return NH_OK;
+    if (tail_blocks == 0 || !s->tail_stream || s->grid < 4) return NH_OK;
     s->tail_blocks = std::min<uint32_t>(tail_blocks, 64);
     int lds_cu = 0, lds_block = 0, khz = 0;
     if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, s->device) !=
@@ -4229,8 +4329,6 @@ int server_tail_setup(nh_server *s, uint32_t tail_blocks) {
     std::memset(s->tail_word_h, 0, 64);
     if (hipHostGetDevicePointer((void **)&s->tail_word_d, h, 0) != hipSuccess)
         return fail(NH_EDEVICE, "tail word mapping failed");
-    if (hipStreamCreateWithFlags(&s->tail_stream, hipStreamNonBlocking) != hipSuccess)
-        return fail(NH_EDEVICE, "tail stream creation failed");
     if (hipEventCreateWithFlags(&s->tail_ev, hipEventDisableTiming) != hipSuccess)
         return fail(NH_EDEVICE, "tail event creation failed");
     return NH_OK;
@@ -4366,12 +4464,22 @@ NH_API int nh_server_create(const nh_server_config *config, void *stream, nh_ser
         return code;
     };
     if (hipGetDevice(&s->device) != hipSuccess) return bail(fail(NH_EDEVICE, "no HIP device"));
-    if (stream) {
+    // A tail lane's kernel runs for as long as tails walk, and a hardware queue runs its kernels in
+    // order: the rounds and the lane each get a stream of the server's own, created one after the
+    // other so that the runtime puts them on different hardware queues.  The caller's stream then
+    // only orders submissions (the server stream waits for the caller's work at each submit).
+    const bool want_tail = config->tail_blocks > 0 && s->cfg.solo_max > 0;
+    if (stream && !want_tail) {
         s->stream = (hipStream_t)stream;
     } else {
         if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
             return bail(fail(NH_EDEVICE, "stream creation failed"));
         s->own_stream = true;
+        s->user_stream = (hipStream_t)stream;
+        if (want_tail && hipStreamCreateWithFlags(&s->tail_stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(NH_EDEVICE, "tail stream creation failed"));
+        if (s->user_stream && hipEventCreateWithFlags(&s->submit_ev, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(NH_EDEVICE, "event creation failed"));
     }
     s->L = layout(s->cap_lin, s->max_jobs);
     if (hipMalloc(&s->ws, s->L.total) != hipSuccess)
@@ -4487,6 +4595,10 @@ NH_API int nh_server_submit(nh_server *s, const nh_job *job, uint64_t tag) {
         return fail(NH_EINVAL, "job of %llu lineages exceeds the server capacity %llu", (unsigned long long)job->n,
                     (unsigned long long)s->cap_lin);
     if (pow2_at_least(2 * job->n, 64) > s->rich_total) return fail(NH_EINVAL, "job too large for the species pool");
+    if (s->user_stream) { // the job's buffers may still be written by work on the caller's stream
+        HIP_TRY(hipEventRecord(s->submit_ev, s->user_stream));
+        HIP_TRY(hipStreamWaitEvent(s->stream, s->submit_ev, 0));
+    }
     s->pending.emplace_back(*job, tag);
     return NH_OK;
 }

@@ -106,7 +106,9 @@ def test_event_stream_equals_the_oracle(B, torch_mod, k):
         _assert_same_stream(got, ref_ev, ref_co, f"{name} coop_max={coop}")
 
 
-def test_event_stream_of_a_mixed_batch_and_a_short_buffer(B, torch_mod):
+@pytest.mark.parametrize("endgame", [0, 64, 4096], ids=["no endgame", "endgame 64", "endgame 4096"])
+def test_event_stream_of_a_mixed_batch_and_a_short_buffer(B, torch_mod, endgame):
+    """Lineages finished by the endgame (walked on without merging) leave the same reduced stream."""
     picks = [0, 1, 7, 8, 9]
     spec, refs = [], []
     for j, k in enumerate(picks):
@@ -116,7 +118,7 @@ def test_event_stream_of_a_mixed_batch_and_a_short_buffer(B, torch_mod):
         spec.append((scn, seed + 100 * j, samples))
         refs.append(osc.event_stream(seed + 100 * j, samples))
     say("mixed batch of", len(spec))
-    jobs, ws, _, _ = _run(B, torch_mod, spec, B.make_config(solo_max=32))
+    jobs, ws, _, _ = _run(B, torch_mod, spec, B.make_config(solo_max=32, endgame=endgame))
     for got, (ref_ev, ref_co) in zip(B.event_stream(jobs, ws), refs):
         _assert_same_stream(got, ref_ev, ref_co)
     # room for half of each job's events: the first half is written and the counts are whole

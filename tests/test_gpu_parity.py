@@ -364,7 +364,8 @@ def test_solo_tails_never_change_results(B, torch_mod):
     ws = torch.empty(B.workspace_bytes(n_total, len(wls)), dtype=torch.uint8, device=dev)
     base = None
     for cfg in (dict(), dict(solo_max=64), dict(solo_max=4096, solo_step=8.0), dict(solo_max=64, solo_step=1e5),
-                dict(solo_max=1 << 30, solo_step=64.0, coop_max=1)):
+                dict(solo_max=1 << 30, solo_step=64.0, coop_max=1), dict(endgame=4096),
+                dict(endgame=64, solo_max=64), dict(endgame=1, launch=B.NH_LAUNCH_GRAPHS)):
         say("solo setting", cfg, "lineages", n_total)
         outs = [torch.empty(len(w.samples), dtype=torch.int64, device=dev) for w in wls]
         rich = torch.zeros(len(wls), dtype=torch.int64, device=dev)
