@@ -559,8 +559,7 @@ def scn_table_sized(torch, dev, nbytes):
 
 # the batched form stays one persistent launch per run; these are its tuned knobs
 BATCH_KNOBS = {"solo_max": [0, 64, 256], "horizon_step_max": [64.0, 256.0, 4096.0],
-               "horizon_growth": [1.25, 1.5, 2.0], "horizon0": [0.5, 2.0], "blocks_per_cu": [2, 4],
-               "endgame": [0, 128, 1024]}
+               "horizon_growth": [1.25, 1.5, 2.0], "horizon0": [0.5, 2.0], "blocks_per_cu": [2, 4]}
 
 
 def batched_form(args, B, W, torch, compare: bool = True) -> dict:
