@@ -498,6 +498,10 @@ const char *nh_last_error(void);
 /* Library version string. */
 const char *nh_version(void);
 
+/* sizeof the public struct of that name (e.g. "nh_config"), 0 for an unknown name: for
+ * bindings to check that their copies of these layouts match the library's. */
+uint64_t nh_struct_bytes(const char *name);
+
 /* Measurement helpers, not part of the method; callers are benchmarks that
  * price the hot path against what the chip sustains.
  * nh_measure_mix_peak: with 8 workgroups of 256 lanes per compute unit, every

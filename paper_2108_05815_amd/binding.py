@@ -123,6 +123,8 @@ _lib.nh_batch_resume.restype = C.c_int
 _lib.nh_event_stream.argtypes = [C.POINTER(nh_job), C.c_uint32, C.c_void_p, C.c_uint64, C.POINTER(nh_stream_out),
                                  C.c_void_p]
 _lib.nh_event_stream.restype = C.c_int
+_lib.nh_struct_bytes.argtypes = [C.c_char_p]
+_lib.nh_struct_bytes.restype = C.c_uint64
 _lib.nh_measure_event_latency.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.POINTER(C.c_double), C.c_void_p]
 _lib.nh_measure_event_latency.restype = C.c_int
 _lib.nh_eval_primitives.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.POINTER(nh_primitive_io), C.c_uint32,
@@ -196,7 +198,8 @@ EXPORTED = ["nh_scenario_create", "nh_scenario_create_implicit", "nh_scenario_de
             "nh_simulate_device", "nh_simulate_async", "nh_simulate_noalloc",
             "nh_simulate", "nh_last_error", "nh_version", "nh_server_bytes", "nh_server_create",
             "nh_server_submit", "nh_server_progress", "nh_server_poll", "nh_server_drain", "nh_server_destroy",
-            "nh_measure_mix_peak", "nh_measure_gather", "nh_measure_event_latency", "nh_eval_primitives"]
+            "nh_measure_mix_peak", "nh_measure_gather", "nh_measure_event_latency", "nh_eval_primitives",
+            "nh_struct_bytes"]
 
 
 class NecsimError(RuntimeError):

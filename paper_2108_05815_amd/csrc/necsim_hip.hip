@@ -2880,6 +2880,20 @@ NH_API const char *nh_last_error(void) { return g_last_error.c_str(); }
 
 NH_API const char *nh_version(void) { return "libnecsim_hip 0.1 (gfx950)"; }
 
+NH_API uint64_t nh_struct_bytes(const char *name) {
+    if (!name) return 0;
+    const std::pair<const char *, uint64_t> sizes[] = {
+        {"nh_habitat", sizeof(nh_habitat)},           {"nh_dispersal", sizeof(nh_dispersal)},
+        {"nh_params", sizeof(nh_params)},             {"nh_config", sizeof(nh_config)},
+        {"nh_stats", sizeof(nh_stats)},               {"nh_job", sizeof(nh_job)},
+        {"nh_event", sizeof(nh_event)},               {"nh_coalescence", sizeof(nh_coalescence)},
+        {"nh_stream_out", sizeof(nh_stream_out)},     {"nh_server_config", sizeof(nh_server_config)},
+        {"nh_completion", sizeof(nh_completion)},     {"nh_primitive_io", sizeof(nh_primitive_io)}};
+    for (const auto &e : sizes)
+        if (std::strcmp(e.first, name) == 0) return e.second;
+    return 0;
+}
+
 NH_API int nh_measure_mix_peak(double *lane_ops_per_s, void *stream_ptr) {
     if (!lane_ops_per_s) return fail(NH_EINVAL, "NULL output");
     hipStream_t stream = (hipStream_t)stream_ptr;

@@ -38,6 +38,17 @@ def test_library_exports_every_declared_symbol(B):
     assert b"gfx950" in B.nh_version()
 
 
+def test_binding_struct_layouts_match_the_library(B):
+    """Every ctypes copy of a public struct has the library's size (a field added on one side only
+    shows here, on the CPU), and the event record dtypes are the C records."""
+    for cls in (B.nh_habitat, B.nh_dispersal, B.nh_params, B.nh_config, B.nh_stats, B.nh_job, B.nh_stream_out,
+                B.nh_server_config, B.nh_completion, B.nh_primitive_io):
+        assert B._lib.nh_struct_bytes(cls.__name__.encode()) == C.sizeof(cls), cls.__name__
+    assert B._lib.nh_struct_bytes(b"nh_event") == B.EVENT_DTYPE.itemsize
+    assert B._lib.nh_struct_bytes(b"nh_coalescence") == B.COALESCENCE_DTYPE.itemsize
+    assert B._lib.nh_struct_bytes(b"no_such_struct") == 0
+
+
 def test_workspace_sizes_grow_with_the_batch(B):
     a = B.workspace_bytes(1000, 1)
     b = B.workspace_bytes(2000, 1)
