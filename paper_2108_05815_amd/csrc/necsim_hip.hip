@@ -1908,19 +1908,22 @@ struct TailArgs {
     uint32_t ring_cap;
     const uint32_t *stop_host;     // host-mapped
     unsigned long long idle_ticks;
-    uint32_t lds_entries;          // table entries each wave may copy to its part of the LDS
+    unsigned long long slice_ticks; // a launch's time slice (its walks are cut and queued again at its end)
+    uint32_t *more_host;            // host-mapped: set when a walk was queued again (the host starts the next slice)
+    uint32_t lds_entries;           // table entries each wave may copy to its part of the LDS
 };
 
 // A lone lineage's walk to its end (lanes 0-7 of a wave; the group's lanes
 // agree throughout): from (p, t) event after event, with no horizon, until it
 // speciates (kStepSpeciated; at = the event's location, t its time) or the
-// search runs away (kStepSlow, flagged in err).  Every 4096 events the walk
+// search runs away (kStepSlow, flagged in err).  Every 512 events the walk
 // reads *stop (when given) and the wall clock (when a deadline is given) and
-// returns kStepOk if either says so.  ev counts the events.
+// returns kStepOk if either says so (a passed deadline also flags kErrTimeout
+// when late_is_error).  ev counts the events.
 template <bool kLds, bool kUni>
 __device__ __forceinline__ uint32_t walk_to_end(const JobView &v, Pos &p, double &t, uint32_t &at, uint32_t &ev,
                                                 uint32_t gl, uint32_t grp_base, uint32_t *err, const uint32_t *stop,
-                                                unsigned long long deadline) {
+                                                unsigned long long deadline, bool late_is_error) {
     uint2 row = table_row<kLds, kUni>(v, p);
     Counters cnt;
     uint32_t st = kStepOk;
@@ -1932,10 +1935,10 @@ __device__ __forceinline__ uint32_t walk_to_end(const JobView &v, Pos &p, double
             t = next_event_time_group(v, p.loc, t, gl, grp_base, err, cnt);
             st = t < 0.0 ? kStepSlow : kStepOk; // kStepSlow now marks a runaway search
         }
-        if ((ev & 4095u) == 0u) {
+        if ((ev & 511u) == 0u) {
             if (stop && __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) return kStepOk;
             if (deadline && wall_clock64() > deadline) {
-                atomicOr(err, kErrTimeout);
+                if (late_is_error) atomicOr(err, kErrTimeout);
                 return kStepOk;
             }
         }
@@ -1968,17 +1971,53 @@ __device__ __forceinline__ bool stage_wave_table(JobView &v, uint32_t entries) {
     return true;
 }
 
-// One walk of the tail lane: lineage g of job jb from (loc0, t0), its result
-// written and the lineage retired; the job's completion goes to the host ring.
+// Queues lineage g at (loc, t) again (a walk cut at the end of its slice) in a
+// free slot; false if none is free.  One lane.
+__device__ __forceinline__ bool tail_requeue(TailQ *T, uint32_t g, uint32_t loc, double t) {
+    uint32_t push = ld_agent(&T->push);
+    while (true) {
+        const uint32_t sq = ld_agent(&T->seq[push % kTailCap]);
+        if (sq != (push < kTailCap ? 0u : ((push - kTailCap + 1u) | kTailCopied))) return false;
+        const uint32_t seen = atomicCAS(&T->push, push, push + 1u);
+        if (seen == push) break;
+        push = seen;
+    }
+    const uint32_t i = push % kTailCap;
+    T->g[i] = g;
+    T->loc[i] = loc;
+    T->t[i] = t;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    st_agent(&T->seq[i], push + 1u);
+    return true;
+}
+
+// One walk of the tail lane: lineage g of job jb from (loc0, t0) until its end
+// (its result written, the lineage retired, the job's completion on the host
+// ring) or the end of the launch's slice (it is queued again where it stands,
+// its events so far counted; if no slot is free it walks on).
 template <bool kLds, bool kUni>
 __device__ __forceinline__ void tail_walk(const TailArgs &A, const JobView &v, uint32_t g, uint32_t jb, uint32_t loc0,
-                                          double t0, uint32_t gl, uint32_t grp_base) {
+                                          double t0, uint32_t gl, uint32_t grp_base, unsigned long long slice_end) {
     TailQ *T = A.q;
     Pos p = pos_from_loc(v, loc0);
     double t = t0;
-    uint32_t at = p.loc, ev = 0;
-    const uint32_t st = walk_to_end<kLds, kUni>(v, p, t, at, ev, gl, grp_base, &A.ctl->error, A.stop_host, 0ull);
-    if (st == kStepOk || gl != 0u) return; // stopped by the host (the server is going away)
+    uint32_t at = p.loc, ev = 0, st = kStepOk;
+    for (unsigned long long end = slice_end;; end = wall_clock64() + A.slice_ticks / 8) {
+        st = walk_to_end<kLds, kUni>(v, p, t, at, ev, gl, grp_base, &A.ctl->error, A.stop_host, end, false);
+        if (st != kStepOk) break;
+        if (__hip_atomic_load(A.stop_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) return; // going away
+        bool queued = false;
+        if (gl == 0u) queued = tail_requeue(T, g, p.loc, t);
+        if (__shfl((int)queued, (int)grp_base, 64)) {
+            if (gl == 0u) {
+                A.lin.events[g] += ev;
+                atomicAdd(&T->done, 1u);
+                __hip_atomic_store(A.more_host, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+            return;
+        }
+    }
+    if (gl != 0u) return;
     write_walk_end(A.lin, v, g, st, at, p, t, ev);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (atomicSub(&A.js[jb].remaining, 1u) == 1u) {
@@ -2017,8 +2056,8 @@ __global__ __launch_bounds__(256) void k_endgame(RoundArgs A, unsigned long long
     double t = A.lin.t[r & 1][g];
     uint32_t at = p.loc, ev = 0;
     const unsigned long long deadline = run_start(ctl) + run_ticks;
-    const uint32_t st = stage ? walk_to_end<true, false>(v, p, t, at, ev, lane, 0u, &ctl->error, nullptr, deadline)
-                              : walk_to_end<false, true>(v, p, t, at, ev, lane, 0u, &ctl->error, nullptr, deadline);
+    const uint32_t st = stage ? walk_to_end<true, false>(v, p, t, at, ev, lane, 0u, &ctl->error, nullptr, deadline, true)
+                              : walk_to_end<false, true>(v, p, t, at, ev, lane, 0u, &ctl->error, nullptr, deadline, true);
     if (st == kStepOk || lane != 0u) return; // past the deadline (flagged)
     write_walk_end(A.lin, v, g, st, at, p, t, ev);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -2034,7 +2073,9 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs A) {
     const uint32_t lane = lane_id(), gl = lane & (kGroup - 1), grp_base = lane & ~(kGroup - 1);
     TailQ *T = A.q;
     unsigned long long idle_from = wall_clock64();
+    const unsigned long long slice_end = idle_from + A.slice_ticks;
     for (uint32_t poll = 0;; ++poll) {
+        if (wall_clock64() >= slice_end) break; // claims nothing past its slice
         uint32_t take = 0, got = 0, stop = 0;
         if (lane == 0) {
             // the stop word lives in host memory: read it seldom (every 32nd poll, about 0.1 ms)
@@ -2066,8 +2107,8 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs A) {
             // else read through the scalar cache
             const bool stage = stage_wave_table(v, A.lds_entries);
             if (lane < kGroup) {
-                if (stage) tail_walk<true, false>(A, v, g, jb, loc0, t0, gl, grp_base);
-                else tail_walk<false, true>(A, v, g, jb, loc0, t0, gl, grp_base);
+                if (stage) tail_walk<true, false>(A, v, g, jb, loc0, t0, gl, grp_base, slice_end);
+                else tail_walk<false, true>(A, v, g, jb, loc0, t0, gl, grp_base, slice_end);
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -4230,7 +4271,8 @@ struct nh_server {
     hipEvent_t tail_ev = nullptr;
     TailQ *d_tail = nullptr;
     unsigned long long *tail_ring_h = nullptr, *tail_ring_d = nullptr;
-    uint32_t *tail_word_h = nullptr, *tail_word_d = nullptr; // [0]: hand-offs (copied each round), [1]: stop
+    uint32_t *tail_word_h = nullptr, *tail_word_d = nullptr; // [0]: hand-offs (copied each round), [1]: stop,
+                                                             // [2]: cut walks queued again
     uint32_t tail_read = 0, tail_seen = 0;
     bool tail_launched = false;
     unsigned long long tail_idle_ticks = 0;
@@ -4348,18 +4390,22 @@ int server_tail_setup(nh_server *s, uint32_t tail_blocks) {
     return NH_OK;
 }
 
-// Starts the tail kernel when hand-offs have come since its last start and it
-// has left: every entry filled before a start is seen by that kernel, which
-// only leaves after idle_ticks with nothing ready.
+// Starts the tail kernel once its last launch has left, if hand-offs have come
+// since that launch started or it queued cut walks again.  A launch sees every
+// entry filled before it started; it leaves at the end of its time slice (so
+// it never holds a hardware queue it may share with the rounds for long) or
+// after idle_ticks with nothing ready.
 int server_tail_kick(nh_server *s) {
     if (!s->tail_stream) return NH_OK;
-    const uint32_t pushed = __atomic_load_n(&s->tail_word_h[0], __ATOMIC_ACQUIRE);
-    if (pushed == s->tail_seen) return NH_OK;
     if (s->tail_launched) {
         const hipError_t q = hipEventQuery(s->tail_ev);
         if (q == hipErrorNotReady) return NH_OK;
         if (q != hipSuccess) return fail(NH_EDEVICE, "tail lane failed: %s", hipGetErrorString(q));
     }
+    const uint32_t pushed = __atomic_load_n(&s->tail_word_h[0], __ATOMIC_ACQUIRE);
+    const uint32_t more = __atomic_load_n(&s->tail_word_h[2], __ATOMIC_ACQUIRE);
+    if (pushed == s->tail_seen && !more) return NH_OK;
+    __atomic_store_n(&s->tail_word_h[2], 0u, __ATOMIC_RELEASE);
     s->tail_seen = pushed;
     TailArgs ta;
     ta.ctl = s->ctl;
@@ -4371,6 +4417,8 @@ int server_tail_kick(nh_server *s) {
     ta.ring_cap = s->max_jobs;
     ta.stop_host = s->tail_word_d + 1;
     ta.idle_ticks = s->tail_idle_ticks;
+    ta.slice_ticks = s->tail_idle_ticks * 40; // 8 ms
+    ta.more_host = s->tail_word_d + 2;
     ta.lds_entries = (uint32_t)(s->tail_lds / (4 * sizeof(uint4)));
     k_tail<<<s->tail_blocks, 256, s->tail_lds, s->tail_stream>>>(ta);
     HIP_TRY(hipGetLastError());

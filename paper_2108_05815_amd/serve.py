@@ -55,10 +55,11 @@ def lineage_capacity_for_budget(budget_bytes: int, max_jobs: int) -> int:
 # rounds short for the jobs that just arrived (a long-lived job then takes more,
 # cheap rounds).  A job down to its last few lineages (solo_max) leaves that
 # schedule: its lineages run 8 lanes each at raised wave priority and advance
-# solo_step per round, so its serial tail is not paced by young jobs' rounds.
-# The batched form, which only cares about the total, prefers a large cap; the
-# autotuner chooses per workload.
-SERVE_DEFAULTS = {"horizon_step_max": 64.0, "solo_max": 256, "solo_step": 512.0}
+# solo_step per round (a short step keeps the rounds short too), and its last
+# lineage leaves for the tail lane, so its serial tail is not paced by young
+# jobs' rounds.  The batched form, which only cares about the total, prefers a
+# large cap; the autotuner chooses per workload.
+SERVE_DEFAULTS = {"horizon_step_max": 64.0, "solo_max": 256, "solo_step": 256.0}
 
 
 def table_bytes_estimate(spec: dict) -> int:
