@@ -1881,19 +1881,17 @@ __global__ void k_run_reset(Ctl *ctl) {
     }
 }
 
-// Single-thread epilogue of a round: publish the survivor count to the
-// host-mapped status word and new job completions to the host-mapped ring,
-// advance the round, reset the next queues.
-// Once a round has left no survivors the run is over (stop = kStopDone): the
-// rounds enqueued past it leave the round number and the status word alone,
-// so the host reads the true last round however late it polls.
 // Tail lane kernel: each wave claims ready entries of the tail queue one at a
-// time and walks the lineage with lanes 0-7 (its table read through the scalar
-// cache) to its speciation or a runaway search, writes the lineage's result
-// and retires it; the lane that retires a job's last lineage publishes the job
-// on the host ring, entry k as ((k + 1) << 32) | job slot.  A wave leaves when
-// it has had nothing to claim for idle_ticks while no wave walked, or when it
-// sees the host's stop word (a walk checks it every 4096 events): waves stay
+// time and walks the lineage with lanes 0-7 (the shared table copied to the
+// wave's part of the LDS when it fits, else read through the scalar cache) to
+// its speciation or a runaway search, writes the lineage's result and retires
+// it; the lane that retires a job's last lineage publishes the job on the host
+// ring, entry k as ((k + 1) << 32) | job slot.  A launch lasts one time slice:
+// it claims nothing after the slice's end, and a walk still running then is
+// queued again where it stands (its events so far counted) and the host-mapped
+// more-flag set, so that the host starts the next slice.  A wave also leaves
+// when it has had nothing to claim for idle_ticks while no wave walked, or when
+// it sees the host's stop word (a walk checks it every 512 events): waves stay
 // for new hand-offs while any walk lasts, the kernel ends once the lane is
 // idle, and the host starts it again when hand-offs come.  Launched with
 // enough dynamic LDS that no round workgroup fits beside it on its compute
@@ -2098,7 +2096,8 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs A) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const uint32_t g = T->g[i], loc0 = T->loc[i];
         const double t0 = T->t[i];
-        __builtin_amdgcn_wave_barrier();
+        // the entry's loads complete before the slot is given back to the producers
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (lane == 0) st_agent(&T->seq[i], (take + 1u) | kTailCopied);
         {
             const uint32_t jb = A.lin.job[g];
@@ -2117,6 +2116,12 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs A) {
     }
 }
 
+// Single-thread epilogue of a round: publish the survivor count to the
+// host-mapped status word and new job completions to the host-mapped ring,
+// advance the round, reset the next queues.
+// Once a round has left no survivors the run is over (stop = kStopDone): the
+// rounds enqueued past it leave the round number and the status word alone,
+// so the host reads the true last round however late it polls.
 // tail/tail_host (servers with a tail lane): the count of tail hand-offs is
 // copied to the host-mapped word, where the host sees that the lane has work.
 __global__ void k_advance(Ctl *ctl, unsigned long long *status_host, const uint32_t *ring, uint32_t ring_cap,
@@ -4283,7 +4288,7 @@ namespace {
 void server_free(nh_server *s) {
     if (!s) return;
     if (s->tail_stream) {
-        // the tail kernel leaves on the stop word (a walk within 4096 events)
+        // the tail kernel leaves on the stop word (a walk within 512 events)
         if (s->tail_word_h) __atomic_store_n(&s->tail_word_h[1], 1u, __ATOMIC_SEQ_CST);
         (void)hipStreamSynchronize(s->tail_stream);
         (void)hipStreamDestroy(s->tail_stream);
