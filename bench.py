@@ -690,18 +690,23 @@ def served_form(args, W, torch) -> dict:
     plain = S.run_plain(arrivals[first], [specs[k] for k in first])
     prefix = served["latencies_s"][first]
     # the slowest measured request again, alone on the idle device: the floor its serial tail sets
+    # (the median of three runs: a lone lineage's per-event time moves by several per cent between runs)
     slow = max(meas, key=lambda k: served["latencies_s"][k])
+    note("served form: the slowest request alone, three times")
     wl, scn = S._build(specs[slow])
     n = scn.individuals
     dev = torch.device("cuda:0")
     s_ids = torch.arange(n, dtype=torch.int64, device=dev)
     out_ids = torch.empty(n, dtype=torch.int64, device=dev)
     ws = torch.empty(B.workspace_bytes(n, 1), dtype=torch.uint8, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = B.batch_run([(scn, wl.seeds[0], s_ids, out_ids, None)], ws)[0]
-    torch.cuda.synchronize()
-    alone_s = time.perf_counter() - t0
+    alone_runs = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = B.batch_run([(scn, wl.seeds[0], s_ids, out_ids, None)], ws)[0]
+        torch.cuda.synchronize()
+        alone_runs.append(time.perf_counter() - t0)
+    alone_s = float(np.median(alone_runs))
     rounds, events, _, _ = served["per_request"][slow]
     served_ms = float(served["latencies_s"][slow] * 1e3)
     return {"workload": f"C5: Poisson 200 req/s, {args.serve_warmup:g} s warm-up then {args.serve_seconds:g} s "
@@ -725,6 +730,7 @@ def served_form(args, W, torch) -> dict:
                              "served_p99_ms": float(np.percentile(prefix, 99) * 1e3)},
             "slowest_request": {"spec": {k: v for k, v in specs[slow].items() if k != "name"},
                                 "served_ms": served_ms, "events": events, "alone_ms": alone_s * 1e3,
+                                "alone_ms_runs": [x * 1e3 for x in alone_runs],
                                 "alone_events": st["events"], "served_over_alone": served_ms / (alone_s * 1e3)}}
 
 
