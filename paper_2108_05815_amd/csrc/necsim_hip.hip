@@ -278,6 +278,49 @@ __device__ __forceinline__ void philox10(uint32_t &c0, uint32_t &c1, uint32_t &c
     }
 }
 
+// The search block of the group step, Philox4x32-10 of the counter
+// (loc, kk, 0, c3) under (k0, k1), as one draw: words 1:0, or words 3:2 when
+// second.  The location is known last; n0 = kk ^ k0 (the first round's word 0,
+// its other product being of 0) and m = 0xD2511F53 * n0 (the second round's
+// first product) do not depend on it and come from the caller, computed before
+// the event's dispersal.  The last round forms only the product the draw needs.
+__device__ __forceinline__ uint64_t philox10_late_loc(uint32_t loc, uint32_t n0, uint64_t m, uint32_t c3,
+                                                      uint32_t k0, uint32_t k1, bool second) {
+    const uint64_t pa = (uint64_t)0xD2511F53u * loc;
+    uint32_t c0 = n0, c1 = 0u, c2 = xor3((uint32_t)(pa >> 32), c3, k1);
+    c3 = (uint32_t)pa;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+    {
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0b = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2b = xor3((uint32_t)(m >> 32), c3, k1);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)m;
+        c0 = n0b;
+        c2 = n2b;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+#pragma unroll
+    for (int i = 2; i < 9; ++i) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0b = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2b = xor3((uint32_t)(p0 >> 32), c3, k1);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0b;
+        c2 = n2b;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    const uint32_t a = second ? c0 : c2, mul = second ? 0xD2511F53u : 0xCD9E8D57u;
+    const uint32_t xo = second ? c3 : c1, kx = second ? k1 : k0;
+    const uint64_t p = (uint64_t)mul * a;
+    return ((uint64_t)(uint32_t)p << 32) | xor3((uint32_t)(p >> 32), xo, kx);
+}
+
 // Dynamic LDS: the shared dispersal table of a single-job round kernel.
 extern __shared__ uint4 nh_lds_table[];
 
@@ -909,6 +952,14 @@ template <bool kLds, bool kUni = false>
 __device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double &t, uint2 &row, uint32_t gl,
                                                uint32_t grp_base, Counters &cnt) {
     const uint64_t tb = (uint64_t)__double_as_longlong(t);
+    // the search's interval and the part of its block that does not depend on the new location
+    const double kf = floor(t * v.inv_dt);
+    const bool wide = !(kf < 2147483648.0);
+    const uint32_t k = wide ? 0u : (uint32_t)kf;
+    const bool q0 = gl < 4u;
+    const uint32_t kk = q0 ? k : k + (gl - 3u);
+    const uint32_t s_n0 = kk ^ v.key0;
+    const uint64_t s_m = (uint64_t)0xD2511F53u * s_n0;
     const uint32_t call = gl & 1u;
     uint32_t a0 = p.loc, a1 = (uint32_t)tb, a2 = (uint32_t)(tb >> 32), a3 = (1u << 30) | call;
     philox10(a0, a1, a2, a3, v.key0, v.key1);
@@ -922,9 +973,6 @@ __device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double 
     disperse<kLds, kUni>(v, q, r1, r2, r3, row);
     row = table_row<kLds, kUni>(v, q);
 
-    const double kf = floor(t * v.inv_dt);
-    const bool wide = !(kf < 2147483648.0);
-    const uint32_t k = wide ? 0u : (uint32_t)kf;
     if (v.sampler == NH_SAMPLER_POISSON) {
         // Lane gl takes interval k + gl whole (every event of a later interval lies beyond t); the
         // lowest interval with an event decides.  No event in k .. k+7 (or a wide index) is slow.
@@ -942,12 +990,8 @@ __device__ __forceinline__ uint32_t group_step(const JobView &v, Pos &p, double 
         t = (spec | slow) ? t : e;
         return spec ? kStepSpeciated : (slow ? kStepSlow : kStepOk);
     }
-    const bool q0 = gl < 4u;
-    const uint32_t kk = q0 ? k : k + (gl - 3u);
-    uint32_t c0 = q.loc, c1 = kk, c2 = 0, c3 = q0 ? (gl >> 1) : 0u;
-    philox10(c0, c1, c2, c3, v.key0, v.key1);
-    const uint64_t first = ((uint64_t)c1 << 32) | c0, second = ((uint64_t)c3 << 32) | c2;
-    const double x = (-log_u53o((q0 && (gl & 1u)) ? second : first)) * v.inv_lambda;
+    const uint64_t draw = philox10_late_loc(q.loc, s_n0, s_m, q0 ? (gl >> 1) : 0u, v.key0, v.key1, q0 && (gl & 1u));
+    const double x = (-log_u53o(draw)) * v.inv_lambda;
     const double x0 = quad_bcast<0>(x), x1 = quad_bcast<1>(x), x2 = quad_bcast<2>(x), x3 = quad_bcast<3>(x);
     const double s0 = kf * v.dt, s1 = s0 + v.dt, s2 = s1 + v.dt, s3 = s2 + v.dt, s4 = s3 + v.dt,
                  s5 = s4 + v.dt;
