@@ -394,10 +394,12 @@ typedef struct {
     uint32_t lookahead;        /* pending jobs past the head that may be admitted first when the head
                                   does not fit (backfill); 0 = strict FIFO */
     nh_config cfg;             /* round-kernel tuning; cfg.rounds_per_graph rounds per launch */
-    uint32_t tail_blocks;      /* tail lane: workgroups (4 waves each, one compute unit each) that walk the
-                                  last lineage of a solo job (cfg.solo_max > 0) outside the rounds, to its
-                                  end; 0 = none.  The lane's kernel runs on a stream of the server's own
-                                  while such lineages exist and leaves when idle */
+    uint32_t tail_blocks;      /* tail lane: workgroups (4 waves each, one compute unit each; at most 64)
+                                  that walk the last lineage of a solo job (cfg.solo_max > 0) whose nu is
+                                  at most 1/16384 outside the rounds, to its end; 0 = none.  The lane's
+                                  kernel runs on a stream of the server's own in launches of 8 ms (a walk
+                                  still going then is queued again and continues in the next launch)
+                                  while such lineages exist, and leaves when idle */
 } nh_server_config;
 
 typedef struct {
